@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of batched homotopy-continuation path tracking on one MI355X.
+
+Workload (the throughput configuration): 512 random dense quadratic systems in
+n = 8 unknowns (45 monomials per equation, coefficients i.i.d. CN(0,1)), each
+solved from the total-degree start system x_i^2 - 1 = 0 with its own random
+unit-modulus gamma: 256 paths per system, 131,072 paths per step.  A "step" is
+one full hc_track_device call: kernel-table preparation, path initialisation,
+tracking (RK4 predictor + Newton corrector + adaptive step) and FP64 endpoint
+refinement, with inputs already resident in HBM.
+
+Prints ONE JSON line.  `value` is mixed-precision (FP32 tracking, FP64 end zone
+and refinement) paths per second; FP64 figures, the per-instance FP64
+comparator, the latency of the single small instance and the CPU oracle
+baseline ride along in the same line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
+SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+
+
+def w_lu(n: int) -> int:
+    """FLOPs of LU with partial pivoting on [A | b] plus back substitution
+    (complex add 2, mul 6, multiply-add 8, reciprocal 8, |re|+|im| compare 2)."""
+    f = sum(8 * (n - k - 1) * (n - k) + 6 * (n - k - 1) + 2 * (n - k) + 8 for k in range(n))
+    return f + sum(8 * (n - k - 1) + 6 for k in range(n))
+
+
+def w_eval(n: int) -> int:
+    """FLOPs to build [H_x | rhs] for a dense quadratic total-degree homotopy as the
+    kernel does: per equation n^2 complex multiply-adds for the Jacobian row, 2n
+    for L.x and x.J (F by Euler's identity), 2n to scale the row by t and 37 for
+    G, G', gamma, the diagonal and the right-hand side."""
+    return n * (8 * n * n + 18 * n + 37)
+
+
+def w_stage(n: int) -> int:
+    return w_eval(n) + w_lu(n)
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch):
+    for _ in range(warmup):
+        ctx.track_device(sysh, p, g, ep, st, info, opts=opts)
+    torch.cuda.synchronize()
+    profs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.track_device(sysh, p, g, ep, st, info, opts=opts)
+        profs.append(ctx.last_profile().as_dict())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, profs
+
+
+def roofline(profs, n, kind):
+    key = "fp32" if kind == "fp32" else "fp64"
+    ms = float(np.mean([p[f"ms_track_{key}"] for p in profs]))
+    launches = float(np.mean([p[f"launches_{key}"] for p in profs]))
+    stages = float(np.mean([p[f"stages_{key}"] for p in profs]))
+    flops = stages * w_stage(n)
+    per_launch_ms = ms / max(launches, 1.0)
+    achieved = flops / launches / (per_launch_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[key]
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": f"k_track<8,{'float' if key == 'fp32' else 'double'}>",
+            "kernel_ms_per_launch": round(per_launch_ms, 4), "launches_per_step": launches,
+            "stages_per_launch": stages / launches, "flops_per_stage": w_stage(n)}
+
+
+def cpu_baseline(S, coef, gam, budget_s=12.0):
+    import oracle
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    oracle.track(S, coef[:2], gam[:2], n_threads=threads)
+    rate_inst = 2 / (time.perf_counter() - t0)
+    k = int(min(len(coef), max(2, round(rate_inst * budget_s))))
+    t0 = time.perf_counter()
+    _, ost, _ = oracle.track(S, coef[:k], gam[:k], n_threads=threads)
+    dt = time.perf_counter() - t0
+    paths = k * 256
+    return {"value": round(paths / dt, 1), "unit": "tracks/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} of the 512 instances ({paths} paths, FP64), {dt:.1f} s, "
+                      f"{threads} threads; success {np.mean(ost == 0):.4f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-instance FP64 comparator and the latency run")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: paths are independent "
+                                   "and the multi-GPU path is not part of this build (--gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+
+    import hc_inputs
+    import paper_2112_03444_amd as hc
+
+    dev = torch.device("cuda:0")
+    S, coef, gam = hc_inputs.workload("dense8_batch512")
+    n_inst, n_start, n = coef.shape[0], 256, S.n
+    p = torch.from_numpy(coef).to(dev)
+    g = torch.from_numpy(gam).to(dev)
+    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+
+    ctx = hc.Context(0)
+    sysh = ctx.load_system(S)
+    ctx.set_profiling(True)
+    res = {}
+    modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
+    for mode in modes:
+        log(f"bench: {mode} batch, {args.warmup} warmup + {args.steps} timed steps")
+        opts = hc.default_opts(precision=mode)
+        dt, profs = time_batch(ctx, sysh, p, g, ep, st, info, opts, args.steps, args.warmup, torch)
+        stn = st.cpu().numpy()
+        inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+        res[mode] = {
+            "ms_per_step": dt * 1e3,
+            "tracks_per_s": n_inst * n_start / dt,
+            "solves_per_s": n_inst / dt,
+            "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+            "escalated": int(inf["escalated"].sum()),
+            "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
+            "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
+            "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64"),
+        }
+        log(f"bench: {mode}: {dt * 1e3:.2f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
+
+    extras = {}
+    if not args.no_extras:
+        # paper-style comparator: plain FP64, one instance per call (one launch set each)
+        log("bench: per-instance FP64 comparator (512 calls)")
+        o64 = hc.default_opts(precision="fp64")
+        ctx.set_profiling(False)
+        ctx.track_device(sysh, p[:1], g[:1], ep[:1], st[:1], info[:1], opts=o64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_inst):
+            ctx.track_device(sysh, p[i:i + 1], g[i:i + 1], ep[i:i + 1], st[i:i + 1], info[i:i + 1], opts=o64)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        extras["per_instance_fp64"] = {"tracks_per_s": n_inst * n_start / dt, "ms_per_instance": dt / n_inst * 1e3}
+        # latency of one small instance (n = 3, 8 paths, FP64)
+        log("bench: single-instance latency (n=3, 8 paths, FP64), 1000 calls")
+        S1, c1, g1 = hc_inputs.workload("dense3_single")
+        sys1 = ctx.load_system(S1)
+        p1 = torch.from_numpy(c1).to(dev)
+        q1 = torch.from_numpy(g1).to(dev)
+        e1 = torch.empty((1, 8, 3), dtype=torch.complex128, device=dev)
+        s1 = torch.empty((1, 8), dtype=torch.int32, device=dev)
+        lat = []
+        for r in range(1050):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.track_device(sys1, p1, q1, e1, s1, None, opts=o64)
+            torch.cuda.synchronize()
+            if r >= 50:
+                lat.append(time.perf_counter() - t0)
+        lat = np.array(lat) * 1e3
+        extras["latency_dense3_single_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                              "p99": float(np.percentile(lat, 99)),
+                                              "repeats": len(lat)}
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        cpu = cpu_baseline(S, coef, gam)
+
+    head = res["mixed"] if "mixed" in res else res["fp64"]
+    out = {
+        "metric": "tracks/s & solves/s (FP32+FP64-refine vs FP64) at 1 GPU; p99 solve latency",
+        "value": round(head["tracks_per_s"], 1),
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64" if "mixed" in res else "fp64",
+        "data": "synthetic",
+        "config": {"workload": "dense8_batch512: 512 random dense quadratic systems, n=8, "
+                               "total-degree start, 256 paths each (131,072 paths)",
+                   "n": n, "n_inst": n_inst, "paths_per_instance": n_start,
+                   "precision": "mixed" if "mixed" in res else "fp64"},
+        "solves_per_s": round(head["solves_per_s"], 2),
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "modes": {m: {k: v for k, v in r.items() if k != "roofline"} | {"roofline": r["roofline"]}
+                  for m, r in res.items()},
+        "peak_scalar_fp32_tflops": SCALAR_FP32_TFLOPS,
+    }
+    if "mixed" in res and "fp64" in res:
+        out["mixed_over_fp64"] = round(res["mixed"]["tracks_per_s"] / res["fp64"]["tracks_per_s"], 3)
+    out.update(extras)
+    if "per_instance_fp64" in extras:
+        out["batched_mixed_over_per_instance_fp64"] = round(
+            head["tracks_per_s"] / extras["per_instance_fp64"]["tracks_per_s"], 2)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * hc.h -- C ABI of the MI355X (gfx950) batched homotopy-continuation tracker.
+ *
+ * The library tracks many independent solution paths x(t), t in [0,1], of a
+ * polynomial homotopy H(x,t) on one GPU and returns each path's endpoint and
+ * status.  The operations follow Chien et al., "GPU-Based Homotopy Continuation
+ * for Minimal Problems in Computer Vision":
+ *   - section 3, Eq. (1): H(x,t) = (1-t) G(x) + t F(x) from a start system G whose
+ *     solutions are known to the target F (here with a unit-modulus gamma on G);
+ *   - section 6 (parallel evaluations): coefficients interpolated linearly between
+ *     a start and a target instance, with dH/dt from the same terms and the
+ *     coefficient differences;
+ *   - section 3, Eqs. (2)-(4) and the 4th-order Runge-Kutta remark: predictor from
+ *     the Davidenko equation H_x dx/dt = -H_t (Eq. 3);
+ *   - section 3, Eqs. (5)-(6): Newton corrector at t + dt;
+ *   - section 6 (linear system solver): LU with partial pivoting on [H_x | rhs].
+ *
+ * Conventions for every call:
+ *   - Functions return hc_status; a negative value is an error, and the message
+ *     of the last error on the calling thread is available from hc_last_error().
+ *     On error no output buffer is written.
+ *   - A per-path failure is not an error: it is reported in status[].
+ *   - The caller owns every buffer passed in; the library copies what it needs.
+ *   - Complex numbers are interleaved (re, im) doubles: hc_c64.
+ *   - A context is not thread-safe: one host thread drives it at a time.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HC_MAX_N 8 /* largest number of unknowns the GPU path handles */
+
+typedef struct {
+    double re, im;
+} hc_c64;
+
+typedef enum {
+    HC_OK = 0,
+    HC_E_INVALID = -1,     /* bad argument (null pointer, size, malformed system)  */
+    HC_E_OOM = -2,         /* device or host allocation failed                     */
+    HC_E_DEVICE = -3,      /* a HIP runtime call failed                            */
+    HC_E_UNSUPPORTED = -4  /* valid request outside what the GPU path implements   */
+} hc_status;
+
+/* Per-path outcome, written to status[]. */
+typedef enum {
+    HC_T_SUCCESS = 0,       /* reached t = 1, refined, finite, residual <= eta_max  */
+    HC_T_AT_INFINITY = 1,   /* ||x||_inf exceeded inf_bound                          */
+    HC_T_MIN_STEP = 2,      /* step size fell below h_min                            */
+    HC_T_MAX_STEPS = 3,     /* accepted + rejected steps reached max_steps           */
+    HC_T_SINGULAR = 4,      /* exactly singular Jacobian during endpoint refinement  */
+    HC_T_NONFINITE = 5,     /* non-finite data (coefficients, start point, tangent)  */
+    HC_T_REFINE_FAILED = 6  /* reached t = 1 but the residual stayed above eta_max   */
+} hc_track_status;
+
+typedef enum {
+    HC_FP64 = 0,  /* complex FP64 for every step                                    */
+    HC_MIXED = 1  /* complex FP32 tracking up to t = 1 - t_end, FP64 end zone, FP64
+                     refinement; FP32 failures are re-tracked in FP64               */
+} hc_precision;
+
+typedef enum {
+    HC_TOTAL_DEGREE = 0, /* H = (1-t) gamma G + t F(x; c(p)), G_i = x_i^d_i - 1,
+                            d_i = degree of equation i; start points generated      */
+    HC_PARAMETER = 1     /* H = F(x; (1-t) c(p0) + t c(p1)), start points supplied   */
+} hc_homotopy_kind;
+
+/* Per-path counters, written to info[] when it is not NULL (32 bytes). */
+typedef struct {
+    int32_t steps;       /* accepted steps                                   */
+    int32_t rejects;     /* rejected steps                                   */
+    int32_t newton_its;  /* corrector iterations while tracking              */
+    int32_t refine_its;  /* Newton iterations of the FP64 endpoint refinement */
+    int32_t escalated;   /* 1 if mixed mode handed the path to FP64 tracking */
+    int32_t reserved;
+    double residual;     /* relative backward error max_i |F_i| / sum_k |c_k||m_k|
+                            at the endpoint; NaN when t = 1 was not reached */
+} hc_track_info;
+
+/* A square polynomial family F(x; p): n equations in n unknowns.
+ * Term k lies in equation term_eq[k] and is c_k * prod_j x_j^term_exp[k*n + j].
+ * Its coefficient is affine in the parameters p (length n_params):
+ *   c_k(p) = coef_const[k] + sum_{e = coef_rowptr[k]}^{coef_rowptr[k+1]-1} coef_val[e] * p[coef_col[e]].
+ * coef_const may be NULL (all zero).  coef_rowptr == NULL selects the identity
+ * map c = p (then n_params must equal n_terms and coef_col/coef_val are ignored).
+ * The GPU path requires every term to have total degree <= 2 and every
+ * equation degree >= 1. */
+typedef struct {
+    int32_t n;
+    int32_t n_terms;
+    const int32_t *term_eq;   /* [n_terms]            */
+    const int32_t *term_exp;  /* [n_terms * n]        */
+    int32_t n_params;
+    int32_t kind;             /* hc_homotopy_kind     */
+    const hc_c64 *coef_const; /* [n_terms] or NULL    */
+    const int32_t *coef_rowptr; /* [n_terms + 1] or NULL */
+    const int32_t *coef_col;  /* [nnz]                */
+    const hc_c64 *coef_val;   /* [nnz]                */
+} hc_system_desc;
+
+/* Tracking options.  hc_default_opts() fills the values the CPU reference is run
+ * with; the paper itself prints no step-control constants. */
+typedef struct {
+    double h0;          /* first step size                                     (0.05)  */
+    double h_min;       /* a rejected step below this fails the path           (1e-7)  */
+    double h_max;       /* largest step                                        (0.1)   */
+    double beta_inc;    /* growth factor after n_inc consecutive accepts       (2)     */
+    double beta_dec;    /* factor applied on a rejected step                   (0.5)   */
+    double tau64;       /* FP64 corrector: ||dx||_2 <= tau (1 + ||x||_2)      (1e-8)  */
+    double tau32;       /* FP32 corrector tolerance in mixed mode              (1e-5)  */
+    double pred_tol;    /* first correction above pred_tol (1 + ||x||_2)
+                           rejects the step (prediction too far off)          (1e-2)  */
+    double tau_refine;  /* refinement stops when ||dx||_2 <= tau_refine (1+||x||_2) (1e-14) */
+    double inf_bound;   /* ||x||_inf above this: path at infinity             (1e7)   */
+    double eta_max;     /* largest residual accepted at the endpoint          (1e-10) */
+    double t_end;       /* mixed mode: FP64 tracking on [1 - t_end, 1]         (0.02)  */
+    int32_t precision;  /* hc_precision                                        (FP64)  */
+    int32_t n_inc;      /* accepted steps before the step grows                (5)     */
+    int32_t max_newton; /* corrector iterations per step                       (3)     */
+    int32_t max_steps;  /* accepted + rejected steps per path                  (5000)  */
+    int32_t max_refine; /* endpoint Newton iterations                          (10)    */
+    int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end (0) */
+    int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
+    int32_t reserved;
+} hc_opts;
+
+typedef struct hc_ctx hc_ctx;
+typedef struct hc_system hc_system;
+
+/* Fills *o with the defaults listed above. */
+void hc_default_opts(hc_opts *o);
+
+/* Message of the last error raised on the calling thread ("" if none).  The
+ * pointer stays valid until the next hc_* call on the same thread. */
+const char *hc_last_error(void);
+
+/* Creates a context bound to HIP device `device`.  *out is owned by the caller
+ * and released with hc_destroy.  Errors: HC_E_INVALID (no such device),
+ * HC_E_DEVICE, HC_E_OOM. */
+hc_status hc_create(int device, hc_ctx **out);
+
+/* Frees the context, its workspace and every system still loaded in it. */
+void hc_destroy(hc_ctx *ctx);
+
+/* Validates and copies a system description (a0: the evaluation tables of
+ * section 6, compiled once per family) and uploads its tables to the device.
+ * *out stays owned by the context until hc_free_system or hc_destroy.
+ * Errors: HC_E_INVALID (malformed description), HC_E_UNSUPPORTED (n > HC_MAX_N,
+ * a term of degree > 2, an equation of degree 0), HC_E_OOM, HC_E_DEVICE. */
+hc_status hc_load_system(hc_ctx *ctx, const hc_system_desc *desc, hc_system **out);
+
+/* Releases a loaded system. */
+hc_status hc_free_system(hc_ctx *ctx, hc_system *sys);
+
+/* Number of unknowns and Bezout number prod_i d_i (the number of total-degree
+ * start points) of a loaded system. */
+hc_status hc_system_dims(const hc_system *sys, int32_t *n, int64_t *bezout);
+
+/* Start points first .. first+count-1 of the total-degree start system
+ * G_i = x_i^d_i - 1 (section 3: start solutions known in closed form).  Point b
+ * writes b in mixed radix (d_1, ..., d_n), x_1 least significant, digits j_i,
+ * and sets x_i = exp(2 pi i j_i / d_i).  out: host [count][n]. */
+hc_status hc_total_degree_start(const hc_system *sys, int64_t first, int64_t count, hc_c64 *out);
+
+/* Tracks n_start paths for each of n_inst target instances (host buffers).
+ *   start:    [n_start][n] start points; NULL for HC_TOTAL_DEGREE (then n_start
+ *             must not exceed the Bezout number and path b starts at point b)
+ *   p_start:  [n_params] start parameters (HC_PARAMETER only, else NULL)
+ *   p_target: [n_inst][n_params] target parameters
+ *   gamma:    [n_inst] start-system multipliers (HC_TOTAL_DEGREE; NULL = 1)
+ *   opts:     NULL = hc_default_opts
+ * Outputs: endpoints [n_inst][n_start][n], status [n_inst][n_start], and
+ * info [n_inst][n_start] when info != NULL.  Blocks until done.
+ * Errors: HC_E_INVALID, HC_E_UNSUPPORTED, HC_E_OOM, HC_E_DEVICE. */
+hc_status hc_track(hc_ctx *ctx, const hc_system *sys,
+                   const hc_c64 *start, int32_t n_start,
+                   const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                   const hc_c64 *gamma, const hc_opts *opts,
+                   hc_c64 *endpoints, int32_t *status, hc_track_info *info);
+
+/* Same as hc_track, but every array argument is a device pointer on the
+ * context's device, and the work is enqueued on `stream` (a hipStream_t; NULL =
+ * the null stream).  Returns once the work is enqueued unless
+ * opts->steps_per_launch > 0, which needs host round trips between launches.
+ * The outputs are valid after the stream has been synchronised.  The library's
+ * workspace is reused by the next call on the same context. */
+hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
+                          const hc_c64 *start, int32_t n_start,
+                          const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                          const hc_c64 *gamma, const hc_opts *opts,
+                          hc_c64 *endpoints, int32_t *status, hc_track_info *info,
+                          void *stream);
+
+/* Event timings of the last hc_track / hc_track_device call on a context with
+ * profiling switched on.  The times come from HIP events recorded on the stream
+ * the kernels ran on; a "stage" is one evaluation of [H_x | rhs] plus one LU solve
+ * for one path (inactive lanes are not counted). */
+typedef struct {
+    float ms_prep;          /* kernel-table preparation                     */
+    float ms_init;          /* path-state initialisation                    */
+    float ms_track_fp32;    /* all FP32 tracking launches (mixed mode)      */
+    float ms_track_fp64;    /* all FP64 tracking launches                   */
+    float ms_refine;        /* endpoint refinement and classification       */
+    int32_t launches_fp32;
+    int32_t launches_fp64;
+    int32_t reserved;
+    int64_t stages_fp32;    /* stages executed by the FP32 launches         */
+    int64_t stages_fp64;    /* stages executed by the FP64 launches         */
+} hc_profile;
+
+/* Switches event timing and stage counting on (enable != 0) or off for the
+ * following calls on this context.  It adds a few events and one atomic per
+ * finished path; the kernels are the same. */
+hc_status hc_set_profiling(hc_ctx *ctx, int32_t enable);
+
+/* Waits for the events of the last profiled call and fills *out.  Errors:
+ * HC_E_INVALID if no profiled call has been made on the context. */
+hc_status hc_last_profile(hc_ctx *ctx, hc_profile *out);
+
+/* Homogenised term tables in the form section 6 describes: each entry (an H_i
+ * or a Jacobian entry) is a sum of K terms s * c[a] * x[m_1] * ... * x[m_M],
+ * where x[n] is an auxiliary variable equal to 1 (pads terms of lower degree)
+ * and missing terms have s = 0.  Input: n_entries polynomials in n variables,
+ * entry e holding terms entry_ptr[e] .. entry_ptr[e+1]-1, term t being
+ * scalar[t] * c[coef[t]] * prod_j x_j^exp[t*n + j].  K and M must be at least
+ * the largest term count and degree.  Output out[e][k][2 + M] = (s, a, m_1..m_M),
+ * 0-based indices, variables in ascending order; host memory.
+ * Errors: HC_E_INVALID. */
+hc_status hc_homogenize(int32_t n, int32_t n_entries, const int32_t *entry_ptr,
+                        const int32_t *scalar, const int32_t *coef, const int32_t *exp,
+                        int32_t K, int32_t M, int32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

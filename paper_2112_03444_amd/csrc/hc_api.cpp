@@ -1,0 +1,698 @@
+// hc_api.cpp -- host side of the C ABI declared in include/hc.h.
+//
+// Owns contexts, loaded systems (their kernel tables on the device), the device
+// workspace that holds the structure-of-arrays path state, and the launch
+// sequence prep -> init -> track (FP32 pass + FP64 pass in mixed mode) -> refine.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hc.h"
+#include "hc_internal.h"
+
+using namespace hcx;
+
+namespace {
+
+thread_local std::string g_err;
+
+hc_status fail(hc_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                 \
+    } while (0)
+
+// A grow-only device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+template <typename T>
+hipError_t upload(T **dst, const T *src, size_t count)
+{
+    *dst = nullptr;
+    if (count == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, count * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct hc_system {
+    int n = 0, n_terms = 0, n_params = 0, kind = 0, T = 0;
+    unsigned deg2 = 0;
+    int64_t bezout = 0;
+    std::vector<int> deg;
+    bool has_const = false, has_map = false;
+    // device copies of the tables
+    int *d_slot_ptr = nullptr, *d_slot_term = nullptr, *d_slot_mult = nullptr;
+    double *d_term_const = nullptr;
+    int *d_map_ptr = nullptr, *d_map_col = nullptr;
+    double *d_map_val = nullptr;
+};
+
+struct hc_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;  // used by the host-buffer entry point
+    std::vector<hc_system *> systems;
+    DevBuf state;   // SoA path state
+    DevBuf coef;    // per-instance kernel tables (FP64 then FP32)
+    DevBuf io;      // device copies of host inputs/outputs for hc_track
+    DevBuf counter; // suspended-path counter, then two stage counters (profiling)
+    // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
+    bool profiling = false;
+    bool profiled_call = false;
+    hipEvent_t ev[6] = {};
+    int launches_fp32 = 0, launches_fp64 = 0;
+    bool had_fp32 = false;
+};
+
+extern "C" {
+
+void hc_default_opts(hc_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->h0 = 0.05;
+    o->h_min = 1e-7;
+    o->h_max = 0.1;
+    o->beta_inc = 2.0;
+    o->beta_dec = 0.5;
+    o->tau64 = 1e-8;
+    o->tau32 = 1e-5;
+    o->pred_tol = 1e-2;
+    o->tau_refine = 1e-14;
+    o->inf_bound = 1e7;
+    o->eta_max = 1e-10;
+    o->t_end = 0.02;
+    o->precision = HC_FP64;
+    o->n_inc = 5;
+    o->max_newton = 3;
+    o->max_steps = 5000;
+    o->max_refine = 10;
+    o->steps_per_launch = 0;
+    o->tracks_per_item = 0;
+}
+
+const char *hc_last_error(void) { return g_err.c_str(); }
+
+hc_status hc_create(int device, hc_ctx **out)
+{
+    g_err.clear();
+    if (!out) return fail(HC_E_INVALID, "hc_create: out is NULL");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(HC_E_INVALID, "hc_create: device %d not in [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    hc_ctx *c = new (std::nothrow) hc_ctx;
+    if (!c) return fail(HC_E_OOM, "hc_create: out of host memory");
+    c->device = device;
+    hipError_t e = hipStreamCreate(&c->own_stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(HC_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return HC_OK;
+}
+
+static void free_system_tables(hc_system *s)
+{
+    (void)hipFree(s->d_slot_ptr);
+    (void)hipFree(s->d_slot_term);
+    (void)hipFree(s->d_slot_mult);
+    (void)hipFree(s->d_term_const);
+    (void)hipFree(s->d_map_ptr);
+    (void)hipFree(s->d_map_col);
+    (void)hipFree(s->d_map_val);
+}
+
+void hc_destroy(hc_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (hc_system *s : c->systems) {
+        free_system_tables(s);
+        delete s;
+    }
+    c->state.release();
+    c->coef.release();
+    c->io.release();
+    c->counter.release();
+    for (hipEvent_t &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
+{
+    g_err.clear();
+    if (!c || !d || !out) return fail(HC_E_INVALID, "hc_load_system: NULL argument");
+    if (d->n < 1) return fail(HC_E_INVALID, "hc_load_system: n = %d", d->n);
+    if (d->n > HC_MAX_N) return fail(HC_E_UNSUPPORTED, "hc_load_system: n = %d > %d", d->n, HC_MAX_N);
+    if (d->n_terms < 1 || !d->term_eq || !d->term_exp)
+        return fail(HC_E_INVALID, "hc_load_system: empty or missing term tables");
+    if (d->kind != HC_TOTAL_DEGREE && d->kind != HC_PARAMETER)
+        return fail(HC_E_INVALID, "hc_load_system: kind = %d", d->kind);
+    if (d->kind == HC_PARAMETER)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: parameter homotopies are not implemented on the GPU yet");
+    if (d->n_params < 0) return fail(HC_E_INVALID, "hc_load_system: n_params = %d", d->n_params);
+    const int n = d->n, nt = d->n_terms;
+    if (!d->coef_rowptr && d->n_params != nt)
+        return fail(HC_E_INVALID, "hc_load_system: identity coefficient map needs n_params == n_terms (%d != %d)",
+                    d->n_params, nt);
+    int nnz = 0;
+    if (d->coef_rowptr) {
+        if (d->coef_rowptr[0] != 0) return fail(HC_E_INVALID, "hc_load_system: coef_rowptr[0] != 0");
+        for (int k = 0; k < nt; k++)
+            if (d->coef_rowptr[k + 1] < d->coef_rowptr[k])
+                return fail(HC_E_INVALID, "hc_load_system: coef_rowptr decreases at %d", k);
+        nnz = d->coef_rowptr[nt];
+        if (nnz > 0 && (!d->coef_col || !d->coef_val))
+            return fail(HC_E_INVALID, "hc_load_system: coef_col/coef_val missing");
+        for (int e = 0; e < nnz; e++)
+            if (d->coef_col[e] < 0 || d->coef_col[e] >= d->n_params)
+                return fail(HC_E_INVALID, "hc_load_system: coef_col[%d] = %d out of range", e, d->coef_col[e]);
+    }
+
+    hc_system *s = new (std::nothrow) hc_system;
+    if (!s) return fail(HC_E_OOM, "hc_load_system: out of host memory");
+    s->n = n;
+    s->n_terms = nt;
+    s->n_params = d->n_params;
+    s->kind = d->kind;
+    s->T = dense_terms(n);
+    s->deg.assign(n, 0);
+
+    // a0: map every term to its slot in the dense kernel tables
+    const int n_slots = n * s->T;
+    std::vector<std::vector<std::pair<int, int>>> slot_terms(n_slots);
+    for (int k = 0; k < nt; k++) {
+        const int i = d->term_eq[k];
+        if (i < 0 || i >= n) {
+            delete s;
+            return fail(HC_E_INVALID, "hc_load_system: term_eq[%d] = %d out of range", k, i);
+        }
+        int deg = 0, a = -1, b = -1;
+        for (int j = 0; j < n; j++) {
+            const int e = d->term_exp[(size_t)k * n + j];
+            if (e < 0) {
+                delete s;
+                return fail(HC_E_INVALID, "hc_load_system: negative exponent in term %d", k);
+            }
+            deg += e;
+            for (int r = 0; r < e && deg <= 2; r++) {
+                if (a < 0) a = j;
+                else b = j;
+            }
+        }
+        if (deg > 2) {
+            delete s;
+            return fail(HC_E_UNSUPPORTED, "hc_load_system: term %d has degree %d > 2", k, deg);
+        }
+        s->deg[i] = std::max(s->deg[i], deg);
+        int slot, mult = 1;
+        if (deg == 0) slot = 0;
+        else if (deg == 1) slot = 1 + a;
+        else {
+            if (b < 0) b = a;
+            if (a > b) std::swap(a, b);
+            slot = quad_slot(n, a, b);
+            if (a == b) mult = 2;  // x_a^2 enters dF/dx_a twice
+        }
+        slot_terms[(size_t)i * s->T + slot].push_back({k, mult});
+    }
+    int64_t bez = 1;
+    for (int i = 0; i < n; i++) {
+        if (s->deg[i] < 1) {
+            delete s;
+            return fail(HC_E_UNSUPPORTED, "hc_load_system: equation %d has degree 0", i);
+        }
+        if (s->deg[i] == 2) s->deg2 |= 1u << i;
+        bez *= s->deg[i];
+    }
+    s->bezout = bez;
+    std::vector<int> slot_ptr(n_slots + 1, 0), slot_term, slot_mult;
+    for (int q = 0; q < n_slots; q++) {
+        slot_ptr[q + 1] = slot_ptr[q] + (int)slot_terms[q].size();
+        for (auto &pr : slot_terms[q]) {
+            slot_term.push_back(pr.first);
+            slot_mult.push_back(pr.second);
+        }
+    }
+
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = upload(&s->d_slot_ptr, slot_ptr.data(), slot_ptr.size());
+    if (e == hipSuccess) e = upload(&s->d_slot_term, slot_term.data(), slot_term.size());
+    if (e == hipSuccess) e = upload(&s->d_slot_mult, slot_mult.data(), slot_mult.size());
+    if (e == hipSuccess && d->coef_const) {
+        s->has_const = true;
+        e = upload(&s->d_term_const, reinterpret_cast<const double *>(d->coef_const), (size_t)nt * 2);
+    }
+    if (e == hipSuccess && d->coef_rowptr) {
+        s->has_map = true;
+        e = upload(&s->d_map_ptr, d->coef_rowptr, (size_t)nt + 1);
+        if (e == hipSuccess) e = upload(&s->d_map_col, d->coef_col, (size_t)nnz);
+        if (e == hipSuccess) e = upload(&s->d_map_val, reinterpret_cast<const double *>(d->coef_val), (size_t)nnz * 2);
+    }
+    if (e != hipSuccess) {
+        free_system_tables(s);
+        delete s;
+        return fail(e == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "hc_load_system: %s", hipGetErrorString(e));
+    }
+    c->systems.push_back(s);
+    *out = s;
+    return HC_OK;
+}
+
+hc_status hc_free_system(hc_ctx *c, hc_system *s)
+{
+    g_err.clear();
+    if (!c || !s) return fail(HC_E_INVALID, "hc_free_system: NULL argument");
+    auto it = std::find(c->systems.begin(), c->systems.end(), s);
+    if (it == c->systems.end()) return fail(HC_E_INVALID, "hc_free_system: system not owned by this context");
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_system_tables(s);
+    delete s;
+    c->systems.erase(it);
+    return HC_OK;
+}
+
+hc_status hc_system_dims(const hc_system *s, int32_t *n, int64_t *bezout)
+{
+    g_err.clear();
+    if (!s) return fail(HC_E_INVALID, "hc_system_dims: NULL system");
+    if (n) *n = s->n;
+    if (bezout) *bezout = s->bezout;
+    return HC_OK;
+}
+
+hc_status hc_total_degree_start(const hc_system *s, int64_t first, int64_t count, hc_c64 *out)
+{
+    g_err.clear();
+    if (!s || (count > 0 && !out)) return fail(HC_E_INVALID, "hc_total_degree_start: NULL argument");
+    if (first < 0 || count < 0 || first + count > s->bezout)
+        return fail(HC_E_INVALID, "hc_total_degree_start: range [%lld, %lld) outside [0, %lld)",
+                    (long long)first, (long long)(first + count), (long long)s->bezout);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t q = 0; q < count; q++) {
+        int64_t r = first + q;
+        for (int i = 0; i < s->n; i++) {
+            const int d = s->deg[i];
+            const int64_t j = r % d;
+            r /= d;
+            hc_c64 v;
+            if (j == 0) v = {1.0, 0.0};
+            else if (2 * j == d) v = {-1.0, 0.0};
+            else v = {std::cos(two_pi * (double)j / d), std::sin(two_pi * (double)j / d)};
+            out[q * s->n + i] = v;
+        }
+    }
+    return HC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tracking
+
+static hc_status check_opts(const hc_opts &o)
+{
+    if (o.precision != HC_FP64 && o.precision != HC_MIXED)
+        return fail(HC_E_INVALID, "opts.precision = %d", o.precision);
+    if (!(o.h0 > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.beta_dec > 0 && o.beta_dec < 1) ||
+        !(o.beta_inc >= 1) || o.n_inc < 1 || o.max_newton < 0 || o.max_steps < 0 || o.max_refine < 0 ||
+        o.steps_per_launch < 0 || o.tracks_per_item < 0)
+        return fail(HC_E_INVALID, "opts: step-control values out of range");
+    if (o.precision == HC_MIXED && !(o.t_end > 0 && o.t_end < 1))
+        return fail(HC_E_INVALID, "opts.t_end = %g must lie in (0, 1) in mixed mode", o.t_end);
+    return HC_OK;
+}
+
+// Paths per wavefront work item.  Each item keeps its 64 lanes busy through lane
+// refill; more paths per item balance better but leave fewer items to spread
+// over the 1024 SIMDs.
+static int choose_tracks_per_item(const hc_opts &o, int n_start, int n_inst)
+{
+    if (o.tracks_per_item > 0) return o.tracks_per_item;
+    (void)n_inst;
+    return std::min(n_start, 64);
+}
+
+static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
+                                   const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                                   const hc_c64 *gamma, const hc_opts *opts_in, hc_c64 *endpoints,
+                                   int32_t *status, hc_track_info *info, hipStream_t st)
+{
+    if (!c || !s) return fail(HC_E_INVALID, "hc_track: NULL context or system");
+    if (n_start < 0 || n_inst < 0) return fail(HC_E_INVALID, "hc_track: negative size");
+    hc_opts o;
+    if (opts_in) o = *opts_in;
+    else hc_default_opts(&o);
+    hc_status rc = check_opts(o);
+    if (rc != HC_OK) return rc;
+    if (s->kind == HC_TOTAL_DEGREE && !start && n_start > s->bezout)
+        return fail(HC_E_INVALID, "hc_track: n_start = %d exceeds the Bezout number %lld", n_start,
+                    (long long)s->bezout);
+    (void)p_start;
+    const long long total = (long long)n_start * n_inst;
+    if (total == 0) return HC_OK;
+    if (!p_target && s->n_params > 0) return fail(HC_E_INVALID, "hc_track: p_target is NULL");
+    if (!endpoints || !status) return fail(HC_E_INVALID, "hc_track: NULL output");
+    HIP_TRY(hipSetDevice(c->device));
+
+    const int n = s->n, T = s->T;
+    const bool mixed = o.precision == HC_MIXED;
+    const int n_slots = n * T;
+
+    // workspace: SoA state, then kernel tables
+    const size_t st_doubles = (size_t)total * (2 * n + 2);
+    const size_t st_ints = (size_t)total * 6;
+    HIP_TRY(c->state.ensure(st_doubles * 8 + st_ints * 4));
+    const size_t coef64 = (size_t)n_inst * n_slots * 2 * sizeof(double);
+    const size_t coef32 = mixed ? (size_t)n_inst * n_slots * 2 * sizeof(float) : 0;
+    HIP_TRY(c->coef.ensure(coef64 + coef32));
+    HIP_TRY(c->counter.ensure(64));
+    unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(static_cast<char *>(c->counter.p) + 16);
+    const bool prof = c->profiling;
+    if (prof) {
+        for (hipEvent_t &e : c->ev)
+            if (!e) HIP_TRY(hipEventCreate(&e));
+        HIP_TRY(hipMemsetAsync(stage_ctr, 0, 2 * sizeof(unsigned long long), st));
+        HIP_TRY(hipEventRecord(c->ev[0], st));
+        c->launches_fp32 = c->launches_fp64 = 0;
+        c->had_fp32 = false;
+    }
+
+    TrackState S;
+    double *dp = static_cast<double *>(c->state.p);
+    S.xr = dp;
+    S.xi = dp + (size_t)total * n;
+    S.t = dp + (size_t)total * 2 * n;
+    S.h = S.t + total;
+    int *ip = reinterpret_cast<int *>(dp + st_doubles);
+    S.succ = ip;
+    S.steps = ip + total;
+    S.rejects = ip + 2 * total;
+    S.nits = ip + 3 * total;
+    S.status = ip + 4 * total;
+    S.escal = ip + 5 * total;
+    double *tab64 = static_cast<double *>(c->coef.p);
+    float *tab32 = mixed ? reinterpret_cast<float *>(static_cast<char *>(c->coef.p) + coef64) : nullptr;
+
+    PrepArgs pa;
+    pa.n = n;
+    pa.T = T;
+    pa.n_inst = n_inst;
+    pa.n_params = s->n_params;
+    pa.n_slots = n_slots;
+    pa.slot_ptr = s->d_slot_ptr;
+    pa.slot_term = s->d_slot_term;
+    pa.slot_mult = s->d_slot_mult;
+    pa.term_const = s->d_term_const;
+    pa.map_ptr = s->d_map_ptr;
+    pa.map_col = s->d_map_col;
+    pa.map_val = s->d_map_val;
+    pa.params = reinterpret_cast<const double *>(p_target);
+    pa.out64 = tab64;
+    pa.out32 = tab32;
+    HIP_TRY(launch_prep(pa, st));
+    if (prof) HIP_TRY(hipEventRecord(c->ev[1], st));
+
+    InitArgs ia;
+    ia.n = n;
+    ia.n_start = n_start;
+    ia.total = total;
+    ia.deg2 = s->deg2;
+    ia.start = reinterpret_cast<const double *>(start);
+    ia.h0 = o.h0;
+    ia.s = S;
+    HIP_TRY(launch_init(ia, st));
+    if (prof) HIP_TRY(hipEventRecord(c->ev[2], st));
+
+    const int tpi = choose_tracks_per_item(o, n_start, n_inst);
+    const int per_inst = (n_start + tpi - 1) / tpi;
+    TrackArgs ta;
+    ta.gamma = reinterpret_cast<const double *>(gamma);
+    ta.deg2 = s->deg2;
+    ta.n_start = n_start;
+    ta.items_per_inst = per_inst;
+    ta.tracks_per_item = tpi;
+    ta.n_items = per_inst * n_inst;
+    ta.total = total;
+    ta.h0 = o.h0;
+    ta.h_min = o.h_min;
+    ta.h_max = o.h_max;
+    ta.beta_inc = o.beta_inc;
+    ta.beta_dec = o.beta_dec;
+    ta.pred_tol = o.pred_tol;
+    ta.inf2 = o.inf_bound * o.inf_bound;
+    ta.n_inc = o.n_inc;
+    ta.max_newton = o.max_newton;
+    ta.max_steps = o.max_steps;
+    ta.s = S;
+    ta.n_suspended = static_cast<unsigned *>(c->counter.p);
+    const int wpb = 4;
+
+    // one pass = launches until no path is left suspended by steps_per_launch
+    auto run_pass = [&](bool fp32, double t_final, int escalate) -> hc_status {
+        ta.coef = fp32 ? (const void *)tab32 : (const void *)tab64;
+        ta.tau = fp32 ? o.tau32 : o.tau64;
+        ta.t_final = t_final;
+        ta.escalate = escalate;
+        ta.launch_steps = o.steps_per_launch;
+        ta.stage_count = prof ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
+        for (;;) {
+            if (o.steps_per_launch > 0) HIP_TRY(hipMemsetAsync(ta.n_suspended, 0, sizeof(unsigned), st));
+            HIP_TRY(launch_track(n, fp32, ta, wpb, st));
+            if (fp32) c->launches_fp32++;
+            else c->launches_fp64++;
+            if (o.steps_per_launch == 0) break;
+            unsigned left = 0;
+            HIP_TRY(hipMemcpyAsync(&left, ta.n_suspended, sizeof left, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (left == 0) break;
+        }
+        return HC_OK;
+    };
+    if (mixed) {
+        rc = run_pass(true, 1.0 - o.t_end, 1);
+        if (rc != HC_OK) return rc;
+        c->had_fp32 = true;
+    }
+    if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
+    rc = run_pass(false, 1.0, 0);
+    if (rc != HC_OK) return rc;
+    if (prof) HIP_TRY(hipEventRecord(c->ev[4], st));
+
+    RefineArgs ra;
+    ra.coef = tab64;
+    ra.gamma = reinterpret_cast<const double *>(gamma);
+    ra.deg2 = s->deg2;
+    ra.n_start = n_start;
+    ra.total = total;
+    ra.max_refine = o.max_refine;
+    ra.tau_refine = o.tau_refine;
+    ra.inf2 = o.inf_bound * o.inf_bound;
+    ra.eta_max = o.eta_max;
+    ra.s = S;
+    ra.endpoints = reinterpret_cast<double *>(endpoints);
+    ra.status = status;
+    ra.info = info;
+    HIP_TRY(launch_refine(n, ra, st));
+    if (prof) {
+        HIP_TRY(hipEventRecord(c->ev[5], st));
+        c->profiled_call = true;
+    }
+    return HC_OK;
+}
+
+extern "C" {
+
+hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
+                          const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                          const hc_c64 *gamma, const hc_opts *opts, hc_c64 *endpoints, int32_t *status,
+                          hc_track_info *info, void *stream)
+{
+    g_err.clear();
+    return track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, opts, endpoints,
+                             status, info, static_cast<hipStream_t>(stream));
+}
+
+hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
+                   const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma,
+                   const hc_opts *opts, hc_c64 *endpoints, int32_t *status, hc_track_info *info)
+{
+    g_err.clear();
+    if (!c || !s) return fail(HC_E_INVALID, "hc_track: NULL context or system");
+    if (n_start < 0 || n_inst < 0) return fail(HC_E_INVALID, "hc_track: negative size");
+    const long long total = (long long)n_start * n_inst;
+    if (total == 0) return HC_OK;
+    if (!endpoints || !status) return fail(HC_E_INVALID, "hc_track: NULL output");
+    if (!p_target && s->n_params > 0) return fail(HC_E_INVALID, "hc_track: p_target is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    const int n = s->n;
+    // device copies: start, p_target, gamma, endpoints, status, info
+    const size_t b_start = start ? (size_t)n_start * n * sizeof(hc_c64) : 0;
+    const size_t b_par = (size_t)n_inst * s->n_params * sizeof(hc_c64);
+    const size_t b_gam = gamma ? (size_t)n_inst * sizeof(hc_c64) : 0;
+    const size_t b_ep = (size_t)total * n * sizeof(hc_c64);
+    const size_t b_st = (size_t)total * sizeof(int32_t);
+    const size_t b_inf = info ? (size_t)total * sizeof(hc_track_info) : 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t need = al(b_start) + al(b_par) + al(b_gam) + al(b_ep) + al(b_st) + al(b_inf);
+    HIP_TRY(c->io.ensure(need));
+    char *base = static_cast<char *>(c->io.p);
+    size_t off = 0;
+    auto take = [&](size_t b) -> void * {
+        if (b == 0) return nullptr;
+        void *p = base + off;
+        off += al(b);
+        return p;
+    };
+    hc_c64 *d_start = static_cast<hc_c64 *>(take(b_start));
+    hc_c64 *d_par = static_cast<hc_c64 *>(take(b_par));
+    hc_c64 *d_gam = static_cast<hc_c64 *>(take(b_gam));
+    hc_c64 *d_ep = static_cast<hc_c64 *>(take(b_ep));
+    int32_t *d_st = static_cast<int32_t *>(take(b_st));
+    hc_track_info *d_inf = static_cast<hc_track_info *>(take(b_inf));
+    hipStream_t st = c->own_stream;
+    if (b_start) HIP_TRY(hipMemcpyAsync(d_start, start, b_start, hipMemcpyHostToDevice, st));
+    if (b_par) HIP_TRY(hipMemcpyAsync(d_par, p_target, b_par, hipMemcpyHostToDevice, st));
+    if (b_gam) HIP_TRY(hipMemcpyAsync(d_gam, gamma, b_gam, hipMemcpyHostToDevice, st));
+    hc_status rc = track_device_impl(c, s, d_start, n_start, p_start, d_par, n_inst, d_gam, opts, d_ep, d_st,
+                                     d_inf, st);
+    if (rc != HC_OK) {
+        (void)hipStreamSynchronize(st);
+        return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(endpoints, d_ep, b_ep, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(status, d_st, b_st, hipMemcpyDeviceToHost, st));
+    if (b_inf) HIP_TRY(hipMemcpyAsync(info, d_inf, b_inf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+hc_status hc_set_profiling(hc_ctx *c, int32_t enable)
+{
+    g_err.clear();
+    if (!c) return fail(HC_E_INVALID, "hc_set_profiling: NULL context");
+    c->profiling = enable != 0;
+    return HC_OK;
+}
+
+hc_status hc_last_profile(hc_ctx *c, hc_profile *out)
+{
+    g_err.clear();
+    if (!c || !out) return fail(HC_E_INVALID, "hc_last_profile: NULL argument");
+    if (!c->profiled_call) return fail(HC_E_INVALID, "hc_last_profile: no profiled call on this context");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipEventSynchronize(c->ev[5]));
+    float ms[5];
+    for (int i = 0; i < 5; i++) HIP_TRY(hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    unsigned long long cnt[2];
+    HIP_TRY(hipMemcpy(cnt, static_cast<char *>(c->counter.p) + 16, sizeof cnt, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->ms_prep = ms[0];
+    out->ms_init = ms[1];
+    out->ms_track_fp32 = c->had_fp32 ? ms[2] : 0.0f;
+    out->ms_track_fp64 = ms[3];
+    out->ms_refine = ms[4];
+    out->launches_fp32 = c->launches_fp32;
+    out->launches_fp64 = c->launches_fp64;
+    out->stages_fp32 = (int64_t)cnt[0];
+    out->stages_fp64 = (int64_t)cnt[1];
+    return HC_OK;
+}
+
+// Homogenised term tables (section 6): see hc.h.
+hc_status hc_homogenize(int32_t n, int32_t n_entries, const int32_t *entry_ptr, const int32_t *scalar,
+                        const int32_t *coef, const int32_t *exp, int32_t K, int32_t M, int32_t *out)
+{
+    g_err.clear();
+    if (n < 1 || n_entries < 0 || K < 1 || M < 1)
+        return fail(HC_E_INVALID, "hc_homogenize: bad sizes n=%d entries=%d K=%d M=%d", n, n_entries, K, M);
+    if (n_entries > 0 && (!entry_ptr || !out)) return fail(HC_E_INVALID, "hc_homogenize: NULL argument");
+    if (n_entries > 0 && entry_ptr[0] != 0) return fail(HC_E_INVALID, "hc_homogenize: entry_ptr[0] != 0");
+    const int W = 2 + M;
+    for (int e = 0; e < n_entries; e++) {
+        const int t0 = entry_ptr[e], t1 = entry_ptr[e + 1];
+        if (t1 < t0) return fail(HC_E_INVALID, "hc_homogenize: entry_ptr decreases at %d", e);
+        if (t1 - t0 > K) return fail(HC_E_INVALID, "hc_homogenize: entry %d has %d terms > K = %d", e, t1 - t0, K);
+        if (t1 > t0 && (!scalar || !coef || !exp)) return fail(HC_E_INVALID, "hc_homogenize: NULL term arrays");
+        for (int t = t0; t < t1; t++) {
+            int deg = 0;
+            for (int j = 0; j < n; j++) {
+                if (exp[(size_t)t * n + j] < 0) return fail(HC_E_INVALID, "hc_homogenize: negative exponent");
+                deg += exp[(size_t)t * n + j];
+            }
+            if (deg > M) return fail(HC_E_INVALID, "hc_homogenize: term %d has degree %d > M = %d", t, deg, M);
+        }
+    }
+    for (int e = 0; e < n_entries; e++) {
+        const int t0 = entry_ptr[e], t1 = entry_ptr[e + 1];
+        for (int k = 0; k < K; k++) {
+            int32_t *row = out + ((size_t)e * K + k) * W;
+            if (t0 + k < t1) {
+                const int t = t0 + k;
+                row[0] = scalar[t];
+                row[1] = coef[t];
+                int m = 0;
+                for (int j = 0; j < n; j++)
+                    for (int r = 0; r < exp[(size_t)t * n + j]; r++) row[2 + m++] = j;
+                while (m < M) row[2 + m++] = n;  // auxiliary variable x_n = 1
+            } else {
+                // padding term: zero scalar, first coefficient, first variable
+                for (int w = 0; w < W; w++) row[w] = 0;
+            }
+        }
+    }
+    return HC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// hc_internal.h -- declarations shared by the host library (hc_api.cpp) and the
+// gfx950 kernels (hc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hc.h"
+
+namespace hcx {
+
+constexpr int kMaxN = HC_MAX_N;
+
+// Terms of one dense quadratic equation in n unknowns: 1, x_1..x_n, x_a x_b (a <= b).
+__host__ __device__ constexpr int dense_terms(int n) { return 1 + n + n * (n + 1) / 2; }
+
+// Position of x_a x_b (a <= b) inside an equation's dense term list.
+__host__ __device__ constexpr int quad_slot(int n, int a, int b)
+{
+    return 1 + n + a * n - a * (a - 1) / 2 + (b - a);
+}
+
+// Track status codes inside the SoA state: the public hc_track_status values
+// (>= 0) are final; these two mean "still going".
+constexpr int kRunning = -1;  // between launches or at the FP32/FP64 hand-over
+constexpr int kReached = -2;  // at t = 1, waiting for refinement
+
+// Structure-of-arrays path state in HBM, path index fastest (coalesced when the
+// lanes of a wavefront hold consecutive paths).  x is FP64 in both precisions.
+struct TrackState {
+    double *xr, *xi;   // [n][total]
+    double *t, *h;     // [total]
+    int *succ, *steps, *rejects, *nits, *status, *escal;  // [total]
+};
+
+// Per-instance coefficients in the layout the dense kernels read ("kernel
+// tables"): for each equation i the dense term list as interleaved complex, with
+// the coefficient of x_a^2 stored doubled (it enters dF_i/dx_a twice).
+struct PrepArgs {
+    int n, T, n_inst, n_params, n_slots;    // n_slots = n * T
+    const int *slot_ptr;      // [n_slots + 1] CSR: terms feeding each slot
+    const int *slot_term;     // [nnz_slot]
+    const int *slot_mult;     // [nnz_slot] 1 or 2
+    const double *term_const; // [n_terms][2] or null
+    const int *map_ptr;       // [n_terms + 1] or null (identity)
+    const int *map_col;
+    const double *map_val;    // [nnz][2]
+    const double *params;     // [n_inst][n_params][2]
+    double *out64;            // [n_inst][n_slots][2]
+    float *out32;             // [n_inst][n_slots][2] or null
+};
+
+struct InitArgs {
+    int n, n_start;
+    long long total;
+    unsigned deg2;            // bit i: equation i has degree 2 (else 1)
+    const double *start;      // [n_start][n][2] or null (total-degree points)
+    double h0;
+    TrackState s;
+};
+
+struct TrackArgs {
+    const void *coef;         // [n_inst][n][T][2] in the tracking precision
+    const double *gamma;      // [n_inst][2] or null (gamma = 1)
+    unsigned deg2;
+    int n_start, items_per_inst, tracks_per_item, n_items;
+    long long total;          // n_inst * n_start: stride of the SoA arrays
+    double t_final;           // 1, or 1 - t_end for the FP32 pass
+    int launch_steps;         // steps per path in this launch, 0 = unlimited
+    int escalate;             // FP32 pass: failures go back to RUNNING for FP64
+    double h0, h_min, h_max, beta_inc, beta_dec, tau, pred_tol, inf2;
+    int n_inc, max_newton, max_steps;
+    TrackState s;
+    unsigned *n_suspended;    // paths left RUNNING by launch_steps
+    unsigned long long *stage_count;  // or null: stages of active lanes, summed
+};
+
+struct RefineArgs {
+    const double *coef;       // FP64 kernel tables
+    const double *gamma;
+    unsigned deg2;
+    int n_start;
+    long long total;
+    int max_refine;
+    double tau_refine, inf2, eta_max;
+    TrackState s;
+    double *endpoints;        // [total][n][2]
+    int *status;              // [total]
+    hc_track_info *info;      // [total] or null
+};
+
+hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
+hipError_t launch_init(const InitArgs &a, hipStream_t st);
+// fp32 selects the complex-FP32 tracker, else complex FP64.
+hipError_t launch_track(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
+hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
+
+}  // namespace hcx

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libhc.so (include/hc.h).
+
+Argument marshalling only: every step of the tracking runs in the library's HIP
+kernels.  If libhc.so is missing the import of the binding fails loudly; there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhc.so")
+
+HC_OK = 0
+HC_TOTAL_DEGREE, HC_PARAMETER = 0, 1
+HC_FP64, HC_MIXED = 0, 1
+(HC_T_SUCCESS, HC_T_AT_INFINITY, HC_T_MIN_STEP, HC_T_MAX_STEPS, HC_T_SINGULAR, HC_T_NONFINITE,
+ HC_T_REFINE_FAILED) = range(7)
+STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
+                "REFINE_FAILED"]
+HC_MAX_N = 8
+
+
+class HcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hc error {code}: {msg}")
+        self.code = code
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_terms", ctypes.c_int32),
+                ("term_eq", ctypes.c_void_p), ("term_exp", ctypes.c_void_p),
+                ("n_params", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("coef_const", ctypes.c_void_p), ("coef_rowptr", ctypes.c_void_p),
+                ("coef_col", ctypes.c_void_p), ("coef_val", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("h0", "h_min", "h_max", "beta_inc", "beta_dec", "tau64", "tau32", "pred_tol",
+                 "tau_refine", "inf_bound", "eta_max", "t_end")] + \
+               [(k, ctypes.c_int32) for k in
+                ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
+                 "steps_per_launch", "tracks_per_item", "reserved")]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_float) for k in
+                ("ms_prep", "ms_init", "ms_track_fp32", "ms_track_fp64", "ms_refine")] + \
+               [("launches_fp32", ctypes.c_int32), ("launches_fp64", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stages_fp32", ctypes.c_int64),
+                ("stages_fp64", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+INFO_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_its", np.int32),
+                       ("refine_its", np.int32), ("escalated", np.int32), ("reserved", np.int32),
+                       ("residual", np.float64)])
+assert INFO_DTYPE.itemsize == 32
+
+_lib = None
+
+
+def lib():
+    """The loaded libhc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
+        # one.  Loading torch first lets libhc bind to that already-loaded runtime,
+        # so the process holds a single HIP runtime shared with torch's allocator.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2112_03444_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.hc_default_opts.restype = None
+        L.hc_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        L.hc_last_error.restype = ctypes.c_char_p
+        L.hc_last_error.argtypes = []
+        L.hc_create.restype = ctypes.c_int
+        L.hc_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.hc_destroy.restype = None
+        L.hc_destroy.argtypes = [P]
+        L.hc_load_system.restype = ctypes.c_int
+        L.hc_load_system.argtypes = [P, ctypes.POINTER(SystemDesc), ctypes.POINTER(P)]
+        L.hc_free_system.restype = ctypes.c_int
+        L.hc_free_system.argtypes = [P, P]
+        L.hc_system_dims.restype = ctypes.c_int
+        L.hc_system_dims.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+        L.hc_total_degree_start.restype = ctypes.c_int
+        L.hc_total_degree_start.argtypes = [P, I64, I64, P]
+        L.hc_track.restype = ctypes.c_int
+        L.hc_track.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P]
+        L.hc_track_device.restype = ctypes.c_int
+        L.hc_track_device.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P]
+        L.hc_set_profiling.restype = ctypes.c_int
+        L.hc_set_profiling.argtypes = [P, I32]
+        L.hc_last_profile.restype = ctypes.c_int
+        L.hc_last_profile.argtypes = [P, ctypes.POINTER(Profile)]
+        L.hc_homogenize.restype = ctypes.c_int
+        L.hc_homogenize.argtypes = [I32, I32, P, P, P, P, I32, I32, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HC_OK:
+        raise HcError(rc, lib().hc_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().hc_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": HC_FP64, "mixed": HC_MIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def homogenize(n: int, entries, K: int, M: int) -> np.ndarray:
+    """Section-6 term tables.  entries: list of polynomials, each a list of
+    (scalar, coef_index, exponent_vector).  Returns int32 [n_entries, K, 2 + M]."""
+    ptr = [0]
+    sc, cf, ex = [], [], []
+    for e in entries:
+        for (s, a, expv) in e:
+            sc.append(int(s))
+            cf.append(int(a))
+            ex.append(np.asarray(expv, np.int32))
+        ptr.append(len(sc))
+    ptr_a = np.asarray(ptr, np.int32)
+    sc_a = np.asarray(sc, np.int32)
+    cf_a = np.asarray(cf, np.int32)
+    ex_a = np.ascontiguousarray(np.stack(ex) if ex else np.zeros((0, n), np.int32), dtype=np.int32)
+    out = np.zeros((len(entries), K, 2 + M), np.int32)
+    _check(lib().hc_homogenize(n, len(entries), _ptr(ptr_a), _ptr(sc_a), _ptr(cf_a), _ptr(ex_a),
+                               K, M, _ptr(out)))
+    return out
+
+
+class System:
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+        n = ctypes.c_int32()
+        b = ctypes.c_int64()
+        _check(lib().hc_system_dims(handle, ctypes.byref(n), ctypes.byref(b)))
+        self.n = n.value
+        self.bezout = b.value
+
+    def total_degree_start(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = self.bezout - first
+        out = np.zeros((count, self.n), np.complex128)
+        _check(lib().hc_total_degree_start(self.handle, first, count, _ptr(out)))
+        return out
+
+
+class Context:
+    """One hc_ctx on HIP device `device`."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hc_create(device, ctypes.byref(h)))
+        self.handle = h
+        self._systems = []
+
+    def close(self):
+        if self.handle:
+            lib().hc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_system(self, system, kind: int = HC_TOTAL_DEGREE, coef_const=None, coef_map=None) -> System:
+        """system: object with n, term_eq [n_terms], term_exp [n_terms, n].
+        coef_map: None (identity, p = coefficients) or (rowptr, col, val) CSR."""
+        te = np.ascontiguousarray(system.term_eq, np.int32)
+        tx = np.ascontiguousarray(system.term_exp, np.int32)
+        keep = [te, tx]
+        d = SystemDesc()
+        d.n = int(system.n)
+        d.n_terms = int(te.shape[0])
+        d.term_eq = te.ctypes.data
+        d.term_exp = tx.ctypes.data
+        d.kind = kind
+        if coef_const is not None:
+            cc = np.ascontiguousarray(coef_const, np.complex128)
+            keep.append(cc)
+            d.coef_const = cc.ctypes.data
+        if coef_map is None:
+            d.n_params = d.n_terms
+        else:
+            rp, col, val, n_params = coef_map
+            rp = np.ascontiguousarray(rp, np.int32)
+            col = np.ascontiguousarray(col, np.int32)
+            val = np.ascontiguousarray(val, np.complex128)
+            keep += [rp, col, val]
+            d.n_params = int(n_params)
+            d.coef_rowptr = rp.ctypes.data
+            d.coef_col = col.ctypes.data if col.size else None
+            d.coef_val = val.ctypes.data if val.size else None
+        h = ctypes.c_void_p()
+        _check(lib().hc_load_system(self.handle, ctypes.byref(d), ctypes.byref(h)))
+        del keep
+        s = System(self, h)
+        self._systems.append(s)
+        return s
+
+    def set_profiling(self, enable: bool = True):
+        _check(lib().hc_set_profiling(self.handle, 1 if enable else 0))
+
+    def last_profile(self) -> Profile:
+        p = Profile()
+        _check(lib().hc_last_profile(self.handle, ctypes.byref(p)))
+        return p
+
+    def free_system(self, s: System):
+        _check(lib().hc_free_system(self.handle, s.handle))
+        self._systems.remove(s)
+
+    def track(self, s: System, p_target, gamma=None, start=None, p_start=None, opts: Optional[Opts] = None,
+              n_start: Optional[int] = None):
+        """Host-buffer hc_track.  p_target [n_inst, n_params]; gamma [n_inst];
+        start [n_start, n] or None (total-degree points).  Returns numpy
+        (endpoints [n_inst, n_start, n], status [n_inst, n_start], info)."""
+        p = np.ascontiguousarray(p_target, np.complex128)
+        if p.ndim == 1:
+            p = p[None, :]
+        n_inst = p.shape[0]
+        g = None if gamma is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(gamma, np.complex128), (n_inst,)))
+        st = None if start is None else np.ascontiguousarray(start, np.complex128).reshape(-1, s.n)
+        if n_start is None:
+            n_start = s.bezout if st is None else st.shape[0]
+        ps = None if p_start is None else np.ascontiguousarray(p_start, np.complex128)
+        ep = np.zeros((n_inst, n_start, s.n), np.complex128)
+        status = np.zeros((n_inst, n_start), np.int32)
+        info = np.zeros((n_inst, n_start), INFO_DTYPE)
+        o = opts if opts is not None else default_opts()
+        _check(lib().hc_track(self.handle, s.handle, _ptr(st), n_start, _ptr(ps), _ptr(p), n_inst, _ptr(g),
+                              ctypes.byref(o), _ptr(ep), _ptr(status), _ptr(info)))
+        return ep, status, info
+
+    def track_device(self, s: System, p_target, gamma, endpoints, status, info=None, start=None,
+                     p_start=None, n_start: Optional[int] = None, opts: Optional[Opts] = None, stream=None):
+        """Device-pointer hc_track_device on torch tensors (complex128 for complex
+        arrays, int32 status, info as a [.., 32]-byte uint8 tensor or None).
+        `stream` is a torch.cuda.Stream (default: the current stream)."""
+        import torch
+
+        def dp(t):
+            return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+        n_inst = p_target.shape[0]
+        if n_start is None:
+            n_start = s.bezout if start is None else start.shape[0]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o = opts if opts is not None else default_opts()
+        _check(lib().hc_track_device(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target),
+                                     n_inst, dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
+                                     ctypes.c_void_p(stream.cuda_stream)))

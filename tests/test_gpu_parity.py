@@ -1,0 +1,235 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on the GPU.
+
+Parity bar (FP64 mode): per instance the same number of finite solutions as the
+oracle and a one-to-one match of the solution sets within 1e-9 relative error
+(the tracker may route a path to another root after rounding differences, so the
+set is what is unique; per-path agreement is checked as a secondary statistic).
+Mixed mode: every finite endpoint has residual <= 1e-10 after FP64 refinement and
+the finite solution sets match the FP64 oracle within 1e-9.
+"""
+import numpy as np
+import pytest
+
+import hc_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import paper_2112_03444_amd as hc
+    return hc
+
+
+@pytest.fixture(scope="module")
+def ctx(hc):
+    c = hc.Context(0)
+    yield c
+    c.close()
+
+
+def rel_match(a, b):
+    """Greedy one-to-one nearest matching of the rows of a onto the rows of b;
+    returns the worst relative distance (inf if the sizes differ)."""
+    if len(a) != len(b):
+        return np.inf
+    b = list(b)
+    worst = 0.0
+    for p in a:
+        d = [np.max(np.abs(p - q)) / max(1.0, np.max(np.abs(q))) for q in b]
+        j = int(np.argmin(d))
+        worst = max(worst, d[j])
+        b.pop(j)
+    return worst
+
+
+def finite_set(ep, st, ok):
+    return ep[st == ok]
+
+
+def check_instance_parity(ep_g, st_g, ep_o, st_o, hc, rel=REL):
+    fg = finite_set(ep_g, st_g, hc.HC_T_SUCCESS)
+    fo = finite_set(ep_o, st_o, oracle.SUCCESS)
+    assert len(fg) == len(fo), (np.bincount(st_g, minlength=7), np.bincount(st_o, minlength=7))
+    w = rel_match(fg, fo)
+    assert w <= rel, w
+    return w
+
+
+def test_config1_single_instance_fp64(hc, ctx):
+    S, coef, gam = hc_inputs.workload("dense3_single")
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam)
+    oep, ost, oinfo = oracle.track(S, coef, gam)
+    assert (st == hc.HC_T_SUCCESS).all()
+    check_instance_parity(ep[0], st[0], oep[0], ost[0], hc)
+    # same start point -> same root, and the same step sequence here
+    np.testing.assert_allclose(ep[0], oep[0], rtol=0, atol=1e-12)
+    assert (info["steps"] == oinfo["steps"]).all()
+    assert (info["rejects"] == oinfo["rejects"]).all()
+    assert np.all(info["residual"] <= 1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_dense_fp64_each_n(hc, ctx, n):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(n, 2, seed=1000 + n)
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam)
+    oep, ost, oinfo = oracle.track(S, coef, gam)
+    for i in range(2):
+        check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
+    same = np.max(np.abs(ep - oep), axis=-1) <= 1e-9 * np.maximum(1, np.abs(oep).max(-1))
+    assert same.mean() >= 0.95
+    ctx.free_system(sysh)
+
+
+@pytest.mark.parametrize("n", [3, 6, 8])
+def test_mixed_mode_residual_and_sets(hc, ctx, n):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(n, 4, seed=2000 + n)
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed"))
+    oep, ost, _ = oracle.track(S, coef, gam)
+    ok = st == hc.HC_T_SUCCESS
+    assert np.all(info["residual"][ok] <= 1e-10)
+    for i in range(4):
+        check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
+
+
+def test_config2_full_batch_fp64_sampled(hc, ctx):
+    """The full 512 x 256 batch in the launch configuration the benchmark times;
+    sampled instances are checked against the oracle, every instance against
+    Bezout (256 distinct finite roots with tiny residual)."""
+    S, coef, gam = hc_inputs.workload("dense8_batch512")
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam)
+    assert ep.shape == (512, 256, 8)
+    frac_ok = (st == hc.HC_T_SUCCESS).mean()
+    assert frac_ok >= 0.999, np.bincount(st.ravel(), minlength=7)
+    for i in range(512):
+        f = ep[i][st[i] == hc.HC_T_SUCCESS]
+        d = np.abs(f[:, None, :] - f[None, :, :]).max(-1) + np.eye(len(f)) * 1e9
+        assert d.min() > 1e-6
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-12)
+    sample = [0, 137, 300, 511]
+    oep, ost, _ = oracle.track(S, coef[sample], gam[sample])
+    for k, i in enumerate(sample):
+        check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
+
+
+def test_config2_full_batch_mixed_sampled(hc, ctx):
+    S, coef, gam = hc_inputs.workload("dense8_batch512")
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed"))
+    ok = st == hc.HC_T_SUCCESS
+    assert ok.mean() >= 0.999, np.bincount(st.ravel(), minlength=7)
+    assert np.all(info["residual"][ok] <= 1e-10)
+    sample = [0, 255, 511]
+    oep, ost, _ = oracle.track(S, coef[sample], gam[sample])
+    for k, i in enumerate(sample):
+        check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_chunked_launches_equal_one_shot(hc, ctx, precision):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(6, 3, seed=31)
+    sysh = ctx.load_system(S)
+    a = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision))
+    b = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision, steps_per_launch=7))
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("tpi", [8, 64, 100, 256])
+def test_tracks_per_item_invariance(hc, ctx, tpi):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(8, 2, seed=41)
+    sysh = ctx.load_system(S)
+    ref = ctx.track(sysh, coef, gam)
+    got = ctx.track(sysh, coef, gam, opts=hc.default_opts(tracks_per_item=tpi))
+    for r, g in zip(ref, got):
+        np.testing.assert_array_equal(r, g)
+
+
+def test_ragged_and_empty(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(7, 3, seed=51)
+    sysh = ctx.load_system(S)
+    # 100 of the 128 start points: a ragged last work item
+    ep, st, info = ctx.track(sysh, coef, gam, n_start=100)
+    full, fst, _ = ctx.track(sysh, coef, gam)
+    np.testing.assert_array_equal(ep, full[:, :100])
+    np.testing.assert_array_equal(st, fst[:, :100])
+    # no instances / no paths: nothing to do, no error
+    e0, s0, _ = ctx.track(sysh, coef[:0], gam[:0])
+    assert e0.shape == (0, 128, 7)
+    e1, s1, _ = ctx.track(sysh, coef, gam, n_start=0)
+    assert e1.shape == (3, 0, 7)
+
+
+def test_supplied_start_points_equal_generated(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(5, 2, seed=61)
+    sysh = ctx.load_system(S)
+    starts = sysh.total_degree_start()
+    for b in range(len(starts)):
+        np.testing.assert_array_equal(starts[b], oracle.total_degree_start(S, b))
+    a = ctx.track(sysh, coef, gam)
+    b = ctx.track(sysh, coef, gam, start=starts)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_failure_statuses(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(3, 1, seed=1)
+    sysh = ctx.load_system(S)
+    bad = coef.copy()
+    bad[0, 4] = np.nan
+    _, st, _ = ctx.track(sysh, bad, gam)
+    assert (st == hc.HC_T_NONFINITE).all()
+    _, st, _ = ctx.track(sysh, coef, gam, opts=hc.default_opts(max_steps=1))
+    assert (st == hc.HC_T_MAX_STEPS).all()
+    _, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(max_newton=0, h_min=0.04))
+    assert (st == hc.HC_T_MIN_STEP).all() and (info["rejects"] == 1).all()
+
+
+def test_path_at_infinity(hc, ctx):
+    # F = (x1 x2 - 1, x1 - 2): Bezout 2, one finite root (2, 1/2)
+    S = hc_inputs.PolySystem(n=2, term_eq=np.array([0, 0, 1, 1], np.int32),
+                             term_exp=np.array([[1, 1], [0, 0], [1, 0], [0, 0]], np.int32))
+    c = np.array([[1, -1, 1, -2]], np.complex128)
+    g = np.array([np.exp(0.7j)])
+    sysh = ctx.load_system(S)
+    assert sysh.bezout == 2
+    ep, st, _ = ctx.track(sysh, c, g)
+    _, ost, _ = oracle.track(S, c, g)
+    assert sorted(st[0].tolist()) == sorted(ost[0].tolist()) == [hc.HC_T_SUCCESS, hc.HC_T_AT_INFINITY]
+    np.testing.assert_allclose(ep[0][st[0] == 0][0], [2, 0.5], rtol=1e-12)
+
+
+def test_load_system_errors(hc, ctx):
+    S9 = hc_inputs.dense_quadratic_system(9)
+    with pytest.raises(hc.HcError):
+        ctx.load_system(S9)  # n > HC_MAX_N
+    cubic = hc_inputs.PolySystem(n=1, term_eq=np.array([0], np.int32), term_exp=np.array([[3]], np.int32))
+    with pytest.raises(hc.HcError):
+        ctx.load_system(cubic)
+
+
+def test_device_entry_point_matches_host(hc, ctx):
+    import torch
+    S, coef, gam = hc_inputs.dense_quadratic_instances(6, 4, seed=71)
+    sysh = ctx.load_system(S)
+    ref = ctx.track(sysh, coef, gam)
+    dev = torch.device("cuda:0")
+    p = torch.from_numpy(coef).to(dev)
+    g = torch.from_numpy(gam).to(dev)
+    ep = torch.empty((4, 64, 6), dtype=torch.complex128, device=dev)
+    st = torch.empty((4, 64), dtype=torch.int32, device=dev)
+    info = torch.empty((4, 64, 32), dtype=torch.uint8, device=dev)
+    ctx.track_device(sysh, p, g, ep, st, info)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ep.cpu().numpy(), ref[0])
+    np.testing.assert_array_equal(st.cpu().numpy(), ref[1])
+    inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(4, 64)
+    np.testing.assert_array_equal(inf["steps"], ref[2]["steps"])
