@@ -60,8 +60,9 @@ typedef enum {
 
 typedef enum {
     HC_FP64 = 0,  /* complex FP64 for every step                                    */
-    HC_MIXED = 1  /* complex FP32 tracking up to t = 1 - t_end, FP64 end zone, FP64
-                     refinement; FP32 failures are re-tracked in FP64               */
+    HC_MIXED = 1  /* complex FP32 tracking up to t = 1 - t_end (FP64 t and step
+                     size), then FP64 to t = 1 and FP64 refinement; a path FP32
+                     cannot finish is re-tracked in FP64 from its last point      */
 } hc_precision;
 
 typedef enum {
@@ -112,13 +113,13 @@ typedef struct {
     double beta_inc;    /* growth factor after n_inc consecutive accepts       (2)     */
     double beta_dec;    /* factor applied on a rejected step                   (0.5)   */
     double tau64;       /* FP64 corrector: ||dx||_2 <= tau (1 + ||x||_2)      (1e-8)  */
-    double tau32;       /* FP32 corrector tolerance in mixed mode              (1e-5)  */
+    double tau32;       /* FP32 corrector tolerance in mixed mode              (1e-4)  */
     double pred_tol;    /* first correction above pred_tol (1 + ||x||_2)
                            rejects the step (prediction too far off)          (1e-2)  */
     double tau_refine;  /* refinement stops when ||dx||_2 <= tau_refine (1+||x||_2) (1e-14) */
     double inf_bound;   /* ||x||_inf above this: path at infinity             (1e7)   */
     double eta_max;     /* largest residual accepted at the endpoint          (1e-10) */
-    double t_end;       /* mixed mode: FP64 tracking on [1 - t_end, 1]         (0.02)  */
+    double t_end;       /* mixed mode: FP64 tracking on [1 - t_end, 1]         (0)     */
     int32_t precision;  /* hc_precision                                        (FP64)  */
     int32_t n_inc;      /* accepted steps before the step grows                (5)     */
     int32_t max_newton; /* corrector iterations per step                       (3)     */
@@ -126,7 +127,8 @@ typedef struct {
     int32_t max_refine; /* endpoint Newton iterations                          (10)    */
     int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end (0) */
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
-    int32_t reserved;
+    int32_t lanes_per_path;   /* 1: one path per lane; 4 or 8: one row of [H_x | rhs]
+                                 per lane, 4 or 8 lanes per path; 0 = autotuned  (0)     */
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;

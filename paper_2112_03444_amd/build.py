@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_kernels.hip"),
+           os.path.join(CSRC, "hc_track_group.hip")]
 ARCH = "gfx950"
 
 

@@ -121,12 +121,12 @@ void hc_default_opts(hc_opts *o)
     o->beta_inc = 2.0;
     o->beta_dec = 0.5;
     o->tau64 = 1e-8;
-    o->tau32 = 1e-5;
+    o->tau32 = 1e-4;
     o->pred_tol = 1e-2;
     o->tau_refine = 1e-14;
     o->inf_bound = 1e7;
     o->eta_max = 1e-10;
-    o->t_end = 0.02;
+    o->t_end = 0.0;
     o->precision = HC_FP64;
     o->n_inc = 5;
     o->max_newton = 3;
@@ -134,6 +134,7 @@ void hc_default_opts(hc_opts *o)
     o->max_refine = 10;
     o->steps_per_launch = 0;
     o->tracks_per_item = 0;
+    o->lanes_per_path = 0;
 }
 
 const char *hc_last_error(void) { return g_err.c_str(); }
@@ -369,19 +370,32 @@ static hc_status check_opts(const hc_opts &o)
         !(o.beta_inc >= 1) || o.n_inc < 1 || o.max_newton < 0 || o.max_steps < 0 || o.max_refine < 0 ||
         o.steps_per_launch < 0 || o.tracks_per_item < 0)
         return fail(HC_E_INVALID, "opts: step-control values out of range");
-    if (o.precision == HC_MIXED && !(o.t_end > 0 && o.t_end < 1))
-        return fail(HC_E_INVALID, "opts.t_end = %g must lie in (0, 1) in mixed mode", o.t_end);
+    if (o.lanes_per_path != 0 && o.lanes_per_path != 1 && o.lanes_per_path != 4 && o.lanes_per_path != 8)
+        return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4 or 8)", o.lanes_per_path);
+    if (o.precision == HC_MIXED && !(o.t_end >= 0 && o.t_end < 1))
+        return fail(HC_E_INVALID, "opts.t_end = %g must lie in [0, 1) in mixed mode", o.t_end);
     return HC_OK;
 }
 
-// Paths per wavefront work item.  Each item keeps its 64 lanes busy through lane
-// refill; more paths per item balance better but leave fewer items to spread
-// over the 1024 SIMDs.
-static int choose_tracks_per_item(const hc_opts &o, int n_start, int n_inst)
+// Lanes per path: one row of [H_x | rhs] per lane (G = 4 for n <= 4, 8 for
+// n <= 8) unless one path per lane is asked for or n = 1.
+static int choose_lanes_per_path(const hc_opts &o, int n)
+{
+    if (n < 2) return 1;
+    if (o.lanes_per_path == 1) return 1;
+    const int g = group_lanes(n);
+    if (o.lanes_per_path != 0 && o.lanes_per_path < g) return -1;  // too few lanes for n rows
+    return g;
+}
+
+// Paths per wavefront work item.  The paths of an item go through the item's
+// lanes (or lane groups) by refill, so more paths per item balance better but
+// leave fewer items to spread over the 1024 SIMDs: aim at 8 paths per group.
+static int choose_tracks_per_item(const hc_opts &o, int n_start, int lanes)
 {
     if (o.tracks_per_item > 0) return o.tracks_per_item;
-    (void)n_inst;
-    return std::min(n_start, 64);
+    const int slots = 64 / lanes;
+    return std::min(n_start, lanes == 1 ? 64 : 8 * slots);
 }
 
 static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
@@ -475,7 +489,9 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     HIP_TRY(launch_init(ia, st));
     if (prof) HIP_TRY(hipEventRecord(c->ev[2], st));
 
-    const int tpi = choose_tracks_per_item(o, n_start, n_inst);
+    const int lanes = choose_lanes_per_path(o, n);
+    if (lanes < 0) return fail(HC_E_INVALID, "opts.lanes_per_path = %d is below n = %d", o.lanes_per_path, n);
+    const int tpi = choose_tracks_per_item(o, n_start, lanes);
     const int per_inst = (n_start + tpi - 1) / tpi;
     TrackArgs ta;
     ta.gamma = reinterpret_cast<const double *>(gamma);
@@ -509,7 +525,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         ta.stage_count = prof ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
         for (;;) {
             if (o.steps_per_launch > 0) HIP_TRY(hipMemsetAsync(ta.n_suspended, 0, sizeof(unsigned), st));
-            HIP_TRY(launch_track(n, fp32, ta, wpb, st));
+            if (lanes == 1) HIP_TRY(launch_track(n, fp32, ta, wpb, st));
+            else HIP_TRY(launch_track_group(n, fp32, ta, wpb, st));
             if (fp32) c->launches_fp32++;
             else c->launches_fp64++;
             if (o.steps_per_launch == 0) break;

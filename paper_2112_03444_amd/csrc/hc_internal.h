@@ -93,6 +93,9 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);
 // fp32 selects the complex-FP32 tracker, else complex FP64.
 hipError_t launch_track(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
+// G lanes per path (one row of [H_x | rhs] per lane); G = group_lanes(n).
+hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
+int group_lanes(int n);
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
 
 }  // namespace hcx

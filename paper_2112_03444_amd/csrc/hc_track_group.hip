@@ -1,0 +1,432 @@
+// hc_track_group.hip -- path tracker with G lanes per path, one row per lane.
+//
+// Mapping: a wavefront holds 64/G paths; lane r of a group (G = 4, 8 or 16,
+// G >= n) owns equation r: its coefficients stay in VGPRs for the whole work
+// item (every group of the wavefront works on the same instance), and each
+// stage it builds row r of the augmented matrix [H_x | rhs].  The LU with
+// partial pivoting then runs across the group (section 6: one row per thread):
+//   * pivot search: a DPP max-reduction over the group of (|Re|+|Im|, row) keys;
+//   * no rows move: the pivot row's remaining entries are broadcast to the group
+//     with ds_bpermute and every not-yet-pivotal row eliminates against them;
+//     each lane remembers the position at which its row became pivotal;
+//   * back substitution walks the positions downwards, the pivot lane of each
+//     position producing one unknown and broadcasting it, so every lane ends
+//     with the whole solution vector.
+// Path state (point, RK4 accumulator, t, h, counters) is replicated in the
+// group's lanes, which take identical decisions on identical data.  Per-stage
+// latency is about G times shorter than with one path per lane, so the long
+// paths of a batch no longer hold a wavefront for G times longer.
+#include "hc_device.h"
+
+namespace hcx {
+
+namespace {
+
+__device__ __forceinline__ unsigned umax(unsigned a, unsigned b) { return a > b ? a : b; }
+
+template <int G>
+__device__ __forceinline__ unsigned group_max(unsigned v)
+{
+    // xor 1 and xor 2 inside quads (quad_perm), then mirror across the half row
+    // (lane i <-> 7-i) and the row (lane i <-> 15-i): every lane ends with the max
+    v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    if (G >= 8) v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    if (G >= 16) v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ double bcast(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> bcast(cx<R> v, int src)
+{
+    return {bcast(v.re, src), bcast(v.im, src)};
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> csel(bool s, cx<R> a, cx<R> b)
+{
+    return {s ? a.re : b.re, s ? a.im : b.im};
+}
+
+constexpr int nquad(int n) { return n * (n + 1) / 2; }
+
+// Row r of [H_x | rhs] at (x, t) for H = (1-t) gamma G + t F (see build_td in
+// hc_kernels.hip for the formulas): the lane's own equation only.
+template <int N, typename R>
+__device__ __forceinline__ void build_row(const cx<R> &c0, const cx<R> (&L)[N], const cx<R> (&Q)[nquad(N)], int r,
+                                          bool d2, cx<R> gam, const cx<R> (&x)[N], R t, bool pred,
+                                          cx<R> (&row)[N + 1])
+{
+    cx<R> Lx = {R(0), R(0)};
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        row[j] = L[j];
+        Lx = cfma(L[j], x[j], Lx);
+    }
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < N; a++) {
+#pragma unroll
+        for (int b = a; b < N; b++) {
+            const cx<R> cq = Q[q++];
+            if (a == b) {
+                row[a] = cfma(cq, x[a], row[a]);
+            } else {
+                row[a] = cfma(cq, x[b], row[a]);
+                row[b] = cfma(cq, x[a], row[b]);
+            }
+        }
+    }
+    cx<R> s = Lx;
+#pragma unroll
+    for (int j = 0; j < N; j++) s = cfma(x[j], row[j], s);
+    const cx<R> F = {fma(R(0.5), s.re, c0.re), fma(R(0.5), s.im, c0.im)};
+    cx<R> xr = x[0];
+#pragma unroll
+    for (int j = 1; j < N; j++) xr = csel(r == j, x[j], xr);
+    cx<R> Gv, dG;
+    if (d2) {
+        Gv = cmul(xr, xr);
+        Gv.re -= R(1);
+        dG = {R(2) * xr.re, R(2) * xr.im};
+    } else {
+        Gv = {xr.re - R(1), xr.im};
+        dG = {R(1), R(0)};
+    }
+    const R omt = R(1) - t;
+    const cx<R> gG = cmul(gam, Gv);
+    const cx<R> gdG = cmul(gam, dG);
+    const cx<R> dterm = {omt * gdG.re, omt * gdG.im};
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        row[j] = cscale(t, row[j]);
+        row[j].re += (j == r) ? dterm.re : R(0);
+        row[j].im += (j == r) ? dterm.im : R(0);
+    }
+    const cx<R> Ht = {F.re - gG.re, F.im - gG.im};
+    const cx<R> H = {fma(t, F.re, omt * gG.re), fma(t, F.im, omt * gG.im)};
+    row[N] = csel(pred, cx<R>{-Ht.re, -Ht.im}, cx<R>{-H.re, -H.im});
+}
+
+// Solves the group's n x n system [A | b] (row r in this lane) by elimination
+// with partial pivoting across the group; every lane receives the whole
+// solution in dx.  Must run with the whole wavefront active.  Returns true if a
+// pivot is (numerically) zero.
+template <int N, int G, typename R>
+__device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base, cx<R> (&dx)[N])
+{
+    constexpr unsigned GM = G - 1;
+    int pos = r < N ? -1 : 4 * G;  // position at which this row became pivotal
+    int pl[N];                     // group-relative lane of the pivot of each position
+    cx<R> inv_own = {R(0), R(0)};
+    bool sing = false;
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        const float v = (float)abs1(row[k]);
+        const unsigned key = pos < 0 ? (0x80000000u | (__float_as_uint(v) & ~GM) | (GM - (unsigned)r)) : 0u;
+        const unsigned kmax = group_max<G>(key);
+        const int p = (int)(GM - (kmax & GM));
+        sing |= ((kmax & 0x7fffffffu & ~GM) == 0u);
+        pl[k] = p;
+        cx<R> P[N + 1];
+#pragma unroll
+        for (int c = k; c <= N; c++) P[c] = bcast(row[c], base + p);
+        const cx<R> inv = crecip(P[k]);
+        const bool piv = (r == p);
+        pos = piv ? k : pos;
+        inv_own = csel(piv, inv, inv_own);
+        cx<R> l = cmul(row[k], inv);
+        l = csel(pos < 0, l, cx<R>{R(0), R(0)});
+#pragma unroll
+        for (int c = k + 1; c <= N; c++) row[c] = cfms(l, P[c], row[c]);
+    }
+    cx<R> b = row[N];
+#pragma unroll
+    for (int k = N - 1; k >= 0; k--) {
+        const cx<R> xk = bcast(cmul(b, inv_own), base + pl[k]);
+        dx[k] = xk;
+        const bool above = pos < k;
+        b = csel(above, cfms(row[k], xk, b), b);
+    }
+    return sing;
+}
+
+}  // namespace
+
+template <int N, int G, typename R>
+__global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
+{
+    static_assert(G == 4 || G == 8 || G == 16, "group size");
+    static_assert(N <= G, "one row per lane");
+    constexpr int T = dense_terms(N);
+    constexpr int NQ = nquad(N);
+    const int lane = threadIdx.x & 63;
+    const int r = lane & (G - 1);
+    const int base = lane - r;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = blockDim.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + wib);
+    if (item >= a.n_items) return;
+    const int inst = item / a.items_per_inst;
+    const int tb = (item - inst * a.items_per_inst) * a.tracks_per_item;
+    const int tend = min(tb + a.tracks_per_item, a.n_start);
+    cx<R> gam = {R(1), R(0)};
+    if (a.gamma) gam = {R(a.gamma[2 * inst]), R(a.gamma[2 * inst + 1])};
+    const long long gbase = (long long)inst * a.n_start;
+    const long long total = a.total;
+    const TrackState S = a.s;
+    const R tau = R(a.tau), pred_tol = R(a.pred_tol);
+
+    // this lane's equation, kept in VGPRs for the whole item
+    cx<R> c0 = {R(0), R(0)}, L[N], Q[NQ];
+#pragma unroll
+    for (int j = 0; j < N; j++) L[j] = {R(0), R(0)};
+#pragma unroll
+    for (int q = 0; q < NQ; q++) Q[q] = {R(0), R(0)};
+    const bool d2 = r < N && ((a.deg2 >> r) & 1u);
+    if (r < N) {
+        const R *ce = static_cast<const R *>(a.coef) + ((size_t)inst * N + r) * T * 2;
+        c0 = {ce[0], ce[1]};
+#pragma unroll
+        for (int j = 0; j < N; j++) L[j] = {ce[2 * (1 + j)], ce[2 * (1 + j) + 1]};
+#pragma unroll
+        for (int q = 0; q < NQ; q++) Q[q] = {ce[2 * (1 + N + q)], ce[2 * (1 + N + q) + 1]};
+    }
+
+    int trk = -1;
+    long long g = 0;
+    cx<R> x[N], xe[N], acc[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) x[j] = xe[j] = acc[j] = {R(1), R(0)};
+    double t = 0.0, h = 0.0, te = 0.0, hu = 0.0, tn = 0.0;
+    int phase = 0, nit = 0, succ = 0, steps = 0, rejects = 0, nits = 0, lsteps = 0, escal = 0;
+    unsigned lstages = 0;
+    int next = tb;
+
+    auto save = [&](int st) {
+        if (r == 0) {
+#pragma unroll
+            for (int j = 0; j < N; j++) {
+                S.xr[j * total + g] = (double)x[j].re;
+                S.xi[j * total + g] = (double)x[j].im;
+            }
+            S.t[g] = t;
+            S.h[g] = h;
+            S.succ[g] = succ;
+            S.steps[g] = steps;
+            S.rejects[g] = rejects;
+            S.nits[g] = nits;
+            S.escal[g] = escal;
+            S.status[g] = st;
+            if (a.stage_count) atomicAdd(a.stage_count, (unsigned long long)lstages);
+        }
+        lstages = 0;
+        trk = -1;
+    };
+    auto begin_step = [&]() {
+        const double rem = a.t_final - t;
+        if (h >= rem) {
+            hu = rem;
+            tn = a.t_final;
+        } else {
+            hu = h;
+            tn = t + h;
+        }
+        phase = 0;
+#pragma unroll
+        for (int j = 0; j < N; j++) xe[j] = x[j];
+        te = t;
+    };
+    // failures the FP32 pass cannot resolve go back to RUNNING for the FP64 pass
+    auto fail = [&](int st) {
+        if (a.escalate && st != HC_T_AT_INFINITY) {
+            escal = 1;
+            h = a.h0;
+            succ = 0;
+            st = kRunning;
+        }
+        save(st);
+    };
+    auto refill = [&]() {
+        for (;;) {
+            const unsigned long long need = ballot(trk < 0 && r == 0);
+            if (need == 0ull || next >= tend) break;
+            const int cand = next + __popcll(need & ((1ull << base) - 1ull));
+            next += __popcll(need);
+            if (trk < 0 && cand < tend) {
+                const long long gg = gbase + cand;
+                if (S.status[gg] == kRunning && S.t[gg] < a.t_final && !(a.escalate && S.escal[gg])) {
+                    trk = cand;
+                    g = gg;
+#pragma unroll
+                    for (int j = 0; j < N; j++) x[j] = {R(S.xr[j * total + g]), R(S.xi[j * total + g])};
+                    t = S.t[g];
+                    h = S.h[g];
+                    succ = S.succ[g];
+                    steps = S.steps[g];
+                    rejects = S.rejects[g];
+                    nits = S.nits[g];
+                    escal = S.escal[g];
+                    lsteps = 0;
+                    if (steps + rejects >= a.max_steps)
+                        fail(HC_T_MAX_STEPS);
+                    else
+                        begin_step();
+                }
+            }
+        }
+    };
+
+    refill();
+    while (ballot(trk >= 0) != 0ull) {
+        const bool act = trk >= 0;
+        cx<R> row[N + 1];
+        build_row<N, R>(c0, L, Q, r, d2, gam, xe, R(te), phase < 4, row);
+        cx<R> dx[N];
+        const bool sing = group_solve<N, G, R>(row, r, base, dx);
+
+        if (act) {
+            lstages++;
+            // 0: stage done, 1: accept the step, 2: reject it, 3: path failed (fst)
+            int ev = 0, fst = 0;
+            if (phase < 4) {
+                bool ok = true;
+#pragma unroll
+                for (int j = 0; j < N; j++) ok = ok && finite(dx[j]);
+                if (sing) {
+                    ev = 2;
+                } else if (phase == 0 && !ok) {
+                    ev = 3;
+                    fst = HC_T_NONFINITE;
+                } else {
+                    const R half = R(0.5 * hu), full = R(hu), sixth = R(hu / 6.0);
+#pragma unroll
+                    for (int j = 0; j < N; j++) {
+                        const R w = (phase == 0 || phase == 3) ? R(1) : R(2);
+                        acc[j].re = phase == 0 ? dx[j].re : fma(w, dx[j].re, acc[j].re);
+                        acc[j].im = phase == 0 ? dx[j].im : fma(w, dx[j].im, acc[j].im);
+                        const R c = phase < 2 ? half : full;
+                        xe[j].re = phase == 3 ? fma(sixth, acc[j].re, x[j].re) : fma(c, dx[j].re, x[j].re);
+                        xe[j].im = phase == 3 ? fma(sixth, acc[j].im, x[j].im) : fma(c, dx[j].im, x[j].im);
+                    }
+                    te = phase == 0 || phase == 1 ? t + 0.5 * hu : tn;
+                    nit = 0;
+                    phase++;
+                    if (phase == 4 && a.max_newton <= 0) ev = 2;
+                }
+            } else if (sing) {
+                ev = 2;
+            } else {
+                R nd = R(0), nx = R(0);
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    xe[j] = {xe[j].re + dx[j].re, xe[j].im + dx[j].im};
+                    nd += abs2(dx[j]);
+                    nx += abs2(xe[j]);
+                }
+                nd = sqrt(nd);
+                nx = sqrt(nx);
+                nit++;
+                nits++;
+                if (nit == 1 && !(nd <= pred_tol * (R(1) + nx)))
+                    ev = 2;
+                else if (nd <= tau * (R(1) + nx))
+                    ev = 1;
+                else if (nit >= a.max_newton)
+                    ev = 2;
+            }
+            bool next_step = false;
+            if (ev == 1) {
+                R big = R(0);
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    x[j] = xe[j];
+                    big = fmax(big, abs2(x[j]));
+                }
+                t = tn;
+                steps++;
+                lsteps++;
+                if (++succ >= a.n_inc) {
+                    h = fmin(h * a.beta_inc, a.h_max);
+                    succ = 0;
+                }
+                if (!((double)big <= a.inf2)) {
+                    ev = 3;
+                    fst = isnan(big) ? HC_T_NONFINITE : HC_T_AT_INFINITY;
+                } else if (t >= a.t_final) {
+                    save(a.t_final >= 1.0 ? kReached : kRunning);
+                } else {
+                    next_step = true;
+                }
+            } else if (ev == 2) {
+                rejects++;
+                lsteps++;
+                succ = 0;
+                h *= a.beta_dec;
+                if (h < a.h_min) {
+                    ev = 3;
+                    fst = HC_T_MIN_STEP;
+                } else {
+                    next_step = true;
+                }
+            }
+            if (next_step) {
+                if (a.launch_steps > 0 && lsteps >= a.launch_steps) {
+                    if (r == 0) atomicAdd(a.n_suspended, 1u);
+                    save(kRunning);
+                } else if (steps + rejects >= a.max_steps) {
+                    ev = 3;
+                    fst = HC_T_MAX_STEPS;
+                } else {
+                    begin_step();
+                }
+            }
+            if (ev == 3) fail(fst);
+        }
+        refill();
+    }
+}
+
+template <int N, int G>
+static hipError_t launch_grp(bool fp32, const TrackArgs &a, int wpb, hipStream_t st)
+{
+    // items are one per wavefront; a work item must hold whole groups
+    const int blocks = (a.n_items + wpb - 1) / wpb;
+    if (fp32)
+        hipLaunchKernelGGL((k_track_grp<N, G, float>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_track_grp<N, G, double>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, int wpb, hipStream_t st)
+{
+    if (a.n_items == 0) return hipSuccess;
+    switch (n) {
+    case 2: return launch_grp<2, 4>(fp32, a, wpb, st);
+    case 3: return launch_grp<3, 4>(fp32, a, wpb, st);
+    case 4: return launch_grp<4, 4>(fp32, a, wpb, st);
+    case 5: return launch_grp<5, 8>(fp32, a, wpb, st);
+    case 6: return launch_grp<6, 8>(fp32, a, wpb, st);
+    case 7: return launch_grp<7, 8>(fp32, a, wpb, st);
+    case 8: return launch_grp<8, 8>(fp32, a, wpb, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int group_lanes(int n) { return n <= 4 ? 4 : 8; }
+
+}  // namespace hcx

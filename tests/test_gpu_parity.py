@@ -73,11 +73,14 @@ def test_config1_single_instance_fp64(hc, ctx):
     assert np.all(info["residual"] <= 1e-13)
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
-def test_dense_fp64_each_n(hc, ctx, n):
+def test_dense_fp64_each_n(hc, ctx, n, lanes):
+    """lanes 0: the default layout (a group of 4 or 8 lanes per path, one matrix
+    row per lane); lanes 1: one path per lane."""
     S, coef, gam = hc_inputs.dense_quadratic_instances(n, 2, seed=1000 + n)
     sysh = ctx.load_system(S)
-    ep, st, info = ctx.track(sysh, coef, gam)
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=lanes))
     oep, ost, oinfo = oracle.track(S, coef, gam)
     for i in range(2):
         check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
@@ -86,11 +89,12 @@ def test_dense_fp64_each_n(hc, ctx, n):
     ctx.free_system(sysh)
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("n", [3, 6, 8])
-def test_mixed_mode_residual_and_sets(hc, ctx, n):
+def test_mixed_mode_residual_and_sets(hc, ctx, n, lanes):
     S, coef, gam = hc_inputs.dense_quadratic_instances(n, 4, seed=2000 + n)
     sysh = ctx.load_system(S)
-    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed"))
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed", lanes_per_path=lanes))
     oep, ost, _ = oracle.track(S, coef, gam)
     ok = st == hc.HC_T_SUCCESS
     assert np.all(info["residual"][ok] <= 1e-10)
@@ -132,23 +136,26 @@ def test_config2_full_batch_mixed_sampled(hc, ctx):
         check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_chunked_launches_equal_one_shot(hc, ctx, precision):
+def test_chunked_launches_equal_one_shot(hc, ctx, precision, lanes):
     S, coef, gam = hc_inputs.dense_quadratic_instances(6, 3, seed=31)
     sysh = ctx.load_system(S)
-    a = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision))
-    b = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision, steps_per_launch=7))
+    a = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision, lanes_per_path=lanes))
+    b = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision=precision, steps_per_launch=7,
+                                                        lanes_per_path=lanes))
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
     np.testing.assert_array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("lanes", [0, 1])
 @pytest.mark.parametrize("tpi", [8, 64, 100, 256])
-def test_tracks_per_item_invariance(hc, ctx, tpi):
+def test_tracks_per_item_invariance(hc, ctx, tpi, lanes):
     S, coef, gam = hc_inputs.dense_quadratic_instances(8, 2, seed=41)
     sysh = ctx.load_system(S)
-    ref = ctx.track(sysh, coef, gam)
-    got = ctx.track(sysh, coef, gam, opts=hc.default_opts(tracks_per_item=tpi))
+    ref = ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=lanes))
+    got = ctx.track(sysh, coef, gam, opts=hc.default_opts(tracks_per_item=tpi, lanes_per_path=lanes))
     for r, g in zip(ref, got):
         np.testing.assert_array_equal(r, g)
 
@@ -233,3 +240,23 @@ def test_device_entry_point_matches_host(hc, ctx):
     np.testing.assert_array_equal(st.cpu().numpy(), ref[1])
     inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(4, 64)
     np.testing.assert_array_equal(inf["steps"], ref[2]["steps"])
+
+
+def test_layouts_agree_on_solution_sets(hc, ctx):
+    """The one-path-per-lane and the row-per-lane layouts evaluate and eliminate in
+    a different order, so endpoints agree to rounding, not bitwise."""
+    S, coef, gam = hc_inputs.dense_quadratic_instances(8, 3, seed=81)
+    sysh = ctx.load_system(S)
+    a = ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=1))
+    b = ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=8))
+    for i in range(3):
+        check_instance_parity(a[0][i], a[1][i], b[0][i], b[1][i], hc)
+
+
+def test_bad_layout_option(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(6, 1, seed=82)
+    sysh = ctx.load_system(S)
+    with pytest.raises(hc.HcError):
+        ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=4))  # 4 lanes < 6 rows
+    with pytest.raises(hc.HcError):
+        ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=3))

@@ -420,3 +420,14 @@ def test_forced_failures():
     assert (st == oracle.MAX_STEPS).all()
     _, st, info = oracle.track(S, c, g, opts=oracle.default_opts(max_newton=0, h_min=0.04))
     assert (st == oracle.MIN_STEP).all() and (info["rejects"] == 1).all()
+
+
+def test_residual_hand_value():
+    # F = x - 2 (terms x and 1, coefficients 1 and -2) at x = 3:
+    # |F| = 1 and sum |c| |m| = 3 + 2, so the relative backward error is 1/5
+    S = hc_inputs.PolySystem(n=1, term_eq=np.array([0, 0], np.int32),
+                             term_exp=np.array([[1], [0]], np.int32))
+    assert abs(oracle.residual(S, np.array([1, -2], np.complex128), np.array([3.0])) - 0.2) < 1e-15
+    # at the root it is exactly zero; a zero denominator with F = 0 counts as zero
+    assert oracle.residual(S, np.array([1, -2], np.complex128), np.array([2.0])) == 0.0
+    assert oracle.residual(S, np.array([0, 0], np.complex128), np.array([2.0])) == 0.0
