@@ -176,6 +176,10 @@ hc_status hc_total_degree_start(const hc_system *sys, int64_t first, int64_t cou
  *   p_target: [n_inst][n_params] target parameters
  *   gamma:    [n_inst] start-system multipliers (HC_TOTAL_DEGREE; NULL = 1)
  *   opts:     NULL = hc_default_opts
+ * For HC_PARAMETER the coefficients move linearly from c(p_start) to
+ * c(p_target[i]) (section 6); start and p_start are required, gamma is ignored,
+ * and the one-path-per-lane layout (lanes_per_path = 1, or n = 1) is not
+ * available (HC_E_UNSUPPORTED).
  * Outputs: endpoints [n_inst][n_start][n], status [n_inst][n_start], and
  * info [n_inst][n_start] when info != NULL.  Blocks until done.
  * Errors: HC_E_INVALID, HC_E_UNSUPPORTED, HC_E_OOM, HC_E_DEVICE. */

@@ -200,8 +200,6 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
         return fail(HC_E_INVALID, "hc_load_system: empty or missing term tables");
     if (d->kind != HC_TOTAL_DEGREE && d->kind != HC_PARAMETER)
         return fail(HC_E_INVALID, "hc_load_system: kind = %d", d->kind);
-    if (d->kind == HC_PARAMETER)
-        return fail(HC_E_UNSUPPORTED, "hc_load_system: parameter homotopies are not implemented on the GPU yet");
     if (d->n_params < 0) return fail(HC_E_INVALID, "hc_load_system: n_params = %d", d->n_params);
     const int n = d->n, nt = d->n_terms;
     if (!d->coef_rowptr && d->n_params != nt)
@@ -410,10 +408,12 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     else hc_default_opts(&o);
     hc_status rc = check_opts(o);
     if (rc != HC_OK) return rc;
-    if (s->kind == HC_TOTAL_DEGREE && !start && n_start > s->bezout)
+    const bool param = s->kind == HC_PARAMETER;
+    if (!param && !start && n_start > s->bezout)
         return fail(HC_E_INVALID, "hc_track: n_start = %d exceeds the Bezout number %lld", n_start,
                     (long long)s->bezout);
-    (void)p_start;
+    if (param && n_start > 0 && n_inst > 0 && (!start || (!p_start && s->n_params > 0)))
+        return fail(HC_E_INVALID, "hc_track: a parameter homotopy needs start points and p_start");
     const long long total = (long long)n_start * n_inst;
     if (total == 0) return HC_OK;
     if (!p_target && s->n_params > 0) return fail(HC_E_INVALID, "hc_track: p_target is NULL");
@@ -428,8 +428,10 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const size_t st_doubles = (size_t)total * (2 * n + 2);
     const size_t st_ints = (size_t)total * 6;
     HIP_TRY(c->state.ensure(st_doubles * 8 + st_ints * 4));
-    const size_t coef64 = (size_t)n_inst * n_slots * 2 * sizeof(double);
-    const size_t coef32 = mixed ? (size_t)n_inst * n_slots * 2 * sizeof(float) : 0;
+    // tables: n_inst target instances (+ one start instance for a parameter homotopy)
+    const int n_tab = n_inst + (param ? 1 : 0);
+    const size_t coef64 = (size_t)n_tab * n_slots * 2 * sizeof(double);
+    const size_t coef32 = mixed ? (size_t)n_tab * n_slots * 2 * sizeof(float) : 0;
     HIP_TRY(c->coef.ensure(coef64 + coef32));
     HIP_TRY(c->counter.ensure(64));
     unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(static_cast<char *>(c->counter.p) + 16);
@@ -476,6 +478,19 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     pa.out64 = tab64;
     pa.out32 = tab32;
     HIP_TRY(launch_prep(pa, st));
+    double *tab64_start = nullptr;
+    float *tab32_start = nullptr;
+    if (param) {
+        // the start instance's tables go after the n_inst target tables
+        tab64_start = tab64 + (size_t)n_inst * n_slots * 2;
+        tab32_start = tab32 ? tab32 + (size_t)n_inst * n_slots * 2 : nullptr;
+        PrepArgs p0 = pa;
+        p0.n_inst = 1;
+        p0.params = reinterpret_cast<const double *>(p_start);
+        p0.out64 = tab64_start;
+        p0.out32 = tab32_start;
+        HIP_TRY(launch_prep(p0, st));
+    }
     if (prof) HIP_TRY(hipEventRecord(c->ev[1], st));
 
     InitArgs ia;
@@ -491,6 +506,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
 
     const int lanes = choose_lanes_per_path(o, n);
     if (lanes < 0) return fail(HC_E_INVALID, "opts.lanes_per_path = %d is below n = %d", o.lanes_per_path, n);
+    if (param && lanes == 1)
+        return fail(HC_E_UNSUPPORTED, "hc_track: parameter homotopies need lanes_per_path 0, 4 or 8 and n >= 2");
     const int tpi = choose_tracks_per_item(o, n_start, lanes);
     const int per_inst = (n_start + tpi - 1) / tpi;
     TrackArgs ta;
@@ -518,6 +535,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     // one pass = launches until no path is left suspended by steps_per_launch
     auto run_pass = [&](bool fp32, double t_final, int escalate) -> hc_status {
         ta.coef = fp32 ? (const void *)tab32 : (const void *)tab64;
+        ta.coef0 = !param ? nullptr : fp32 ? (const void *)tab32_start : (const void *)tab64_start;
         ta.tau = fp32 ? o.tau32 : o.tau64;
         ta.t_final = t_final;
         ta.escalate = escalate;
@@ -598,11 +616,12 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     const size_t b_start = start ? (size_t)n_start * n * sizeof(hc_c64) : 0;
     const size_t b_par = (size_t)n_inst * s->n_params * sizeof(hc_c64);
     const size_t b_gam = gamma ? (size_t)n_inst * sizeof(hc_c64) : 0;
+    const size_t b_p0 = p_start ? (size_t)s->n_params * sizeof(hc_c64) : 0;
     const size_t b_ep = (size_t)total * n * sizeof(hc_c64);
     const size_t b_st = (size_t)total * sizeof(int32_t);
     const size_t b_inf = info ? (size_t)total * sizeof(hc_track_info) : 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t need = al(b_start) + al(b_par) + al(b_gam) + al(b_ep) + al(b_st) + al(b_inf);
+    const size_t need = al(b_start) + al(b_par) + al(b_gam) + al(b_p0) + al(b_ep) + al(b_st) + al(b_inf);
     HIP_TRY(c->io.ensure(need));
     char *base = static_cast<char *>(c->io.p);
     size_t off = 0;
@@ -615,6 +634,7 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     hc_c64 *d_start = static_cast<hc_c64 *>(take(b_start));
     hc_c64 *d_par = static_cast<hc_c64 *>(take(b_par));
     hc_c64 *d_gam = static_cast<hc_c64 *>(take(b_gam));
+    hc_c64 *d_p0 = static_cast<hc_c64 *>(take(b_p0));
     hc_c64 *d_ep = static_cast<hc_c64 *>(take(b_ep));
     int32_t *d_st = static_cast<int32_t *>(take(b_st));
     hc_track_info *d_inf = static_cast<hc_track_info *>(take(b_inf));
@@ -622,7 +642,8 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     if (b_start) HIP_TRY(hipMemcpyAsync(d_start, start, b_start, hipMemcpyHostToDevice, st));
     if (b_par) HIP_TRY(hipMemcpyAsync(d_par, p_target, b_par, hipMemcpyHostToDevice, st));
     if (b_gam) HIP_TRY(hipMemcpyAsync(d_gam, gamma, b_gam, hipMemcpyHostToDevice, st));
-    hc_status rc = track_device_impl(c, s, d_start, n_start, p_start, d_par, n_inst, d_gam, opts, d_ep, d_st,
+    if (b_p0) HIP_TRY(hipMemcpyAsync(d_p0, p_start, b_p0, hipMemcpyHostToDevice, st));
+    hc_status rc = track_device_impl(c, s, d_start, n_start, d_p0, d_par, n_inst, d_gam, opts, d_ep, d_st,
                                      d_inf, st);
     if (rc != HC_OK) {
         (void)hipStreamSynchronize(st);

@@ -61,6 +61,7 @@ struct InitArgs {
 
 struct TrackArgs {
     const void *coef;         // [n_inst][n][T][2] in the tracking precision
+    const void *coef0;        // parameter homotopy: start tables [n][T][2], else null
     const double *gamma;      // [n_inst][2] or null (gamma = 1)
     unsigned deg2;
     int n_start, items_per_inst, tracks_per_item, n_items;

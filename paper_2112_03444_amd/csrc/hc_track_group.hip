@@ -121,6 +121,58 @@ __device__ __forceinline__ void build_row(const cx<R> &c0, const cx<R> (&L)[N], 
     row[N] = csel(pred, cx<R>{-Ht.re, -Ht.im}, cx<R>{-H.re, -H.im});
 }
 
+// Row r of [H_x | rhs] for the parameter homotopy H = F(x; c(t)) with the
+// coefficients interpolated linearly between the start and the target instance
+// (section 6): c(t) = (1-t) c0 + t c1 and H_t = F(x; c1 - c0).  The lane's two
+// coefficient rows are read from the kernel tables each stage.
+// Blended coefficient ct = (1-t) c0 + t c1 of term q, and the coefficient cr of
+// the right-hand side: c1 - c0 for a predictor stage (H_t), ct otherwise (H).
+template <typename R>
+__device__ __forceinline__ void blend_coef(const R *e0, const R *e1, int q, R t, R omt, bool pred, cx<R> &ct,
+                                           cx<R> &cr)
+{
+    const cx<R> a = {e0[2 * q], e0[2 * q + 1]};
+    const cx<R> b = {e1[2 * q], e1[2 * q + 1]};
+    ct = {fma(t, b.re, omt * a.re), fma(t, b.im, omt * a.im)};
+    const cx<R> d = {b.re - a.re, b.im - a.im};
+    cr = csel(pred, d, ct);
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void build_row_param(const R *e0, const R *e1, const cx<R> (&x)[N], R t, bool pred,
+                                                cx<R> (&row)[N + 1])
+{
+    const R omt = R(1) - t;
+    auto coefs = [&](int q, cx<R> &ct, cx<R> &cr) { blend_coef<R>(e0, e1, q, t, omt, pred, ct, cr); };
+    cx<R> ct, cr;
+    coefs(0, ct, cr);
+    cx<R> F = cr;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        coefs(1 + j, ct, cr);
+        row[j] = ct;
+        F = cfma(cr, x[j], F);
+    }
+    int q = 1 + N;
+#pragma unroll
+    for (int a = 0; a < N; a++) {
+#pragma unroll
+        for (int b = a; b < N; b++) {
+            coefs(q++, ct, cr);
+            const cx<R> m = cmul(x[a], x[b]);
+            if (a == b) {
+                row[a] = cfma(ct, x[a], row[a]);
+                F = cfma(cscale(R(0.5), cr), m, F);  // the table holds 2 c_aa
+            } else {
+                row[a] = cfma(ct, x[b], row[a]);
+                row[b] = cfma(ct, x[a], row[b]);
+                F = cfma(cr, m, F);
+            }
+        }
+    }
+    row[N] = {-F.re, -F.im};
+}
+
 // Solves the group's n x n system [A | b] (row r in this lane) by elimination
 // with partial pivoting across the group; every lane receives the whole
 // solution in dx.  Must run with the whole wavefront active.  Returns true if a
@@ -166,7 +218,7 @@ __device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base
 
 }  // namespace
 
-template <int N, int G, typename R>
+template <int N, int G, typename R, bool PARAM>
 __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
 {
     static_assert(G == 4 || G == 8 || G == 16, "group size");
@@ -190,14 +242,17 @@ __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
     const TrackState S = a.s;
     const R tau = R(a.tau), pred_tol = R(a.pred_tol);
 
-    // this lane's equation, kept in VGPRs for the whole item
+    // this lane's equation, kept in VGPRs for the whole item (total degree)
     cx<R> c0 = {R(0), R(0)}, L[N], Q[NQ];
 #pragma unroll
     for (int j = 0; j < N; j++) L[j] = {R(0), R(0)};
 #pragma unroll
     for (int q = 0; q < NQ; q++) Q[q] = {R(0), R(0)};
     const bool d2 = r < N && ((a.deg2 >> r) & 1u);
-    if (r < N) {
+    // parameter homotopy: the lane's start and target rows (padding lanes read row 0)
+    const R *row0 = static_cast<const R *>(a.coef0) + (size_t)(r < N ? r : 0) * T * 2;
+    const R *row1 = static_cast<const R *>(a.coef) + ((size_t)inst * N + (r < N ? r : 0)) * T * 2;
+    if (!PARAM && r < N) {
         const R *ce = static_cast<const R *>(a.coef) + ((size_t)inst * N + r) * T * 2;
         c0 = {ce[0], ce[1]};
 #pragma unroll
@@ -294,7 +349,15 @@ __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
     while (ballot(trk >= 0) != 0ull) {
         const bool act = trk >= 0;
         cx<R> row[N + 1];
-        build_row<N, R>(c0, L, Q, r, d2, gam, xe, R(te), phase < 4, row);
+        if constexpr (PARAM) {
+            // re-derived each stage so the loop-invariant table reads are not all
+            // hoisted out of the loop into registers
+            const R *p0 = row0, *p1 = row1;
+            asm volatile("" : "+v"(p0), "+v"(p1));
+            build_row_param<N, R>(p0, p1, xe, R(te), phase < 4, row);
+        } else {
+            build_row<N, R>(c0, L, Q, r, d2, gam, xe, R(te), phase < 4, row);
+        }
         cx<R> dx[N];
         const bool sing = group_solve<N, G, R>(row, r, base, dx);
 
@@ -403,12 +466,15 @@ __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
 template <int N, int G>
 static hipError_t launch_grp(bool fp32, const TrackArgs &a, int wpb, hipStream_t st)
 {
-    // items are one per wavefront; a work item must hold whole groups
     const int blocks = (a.n_items + wpb - 1) / wpb;
-    if (fp32)
-        hipLaunchKernelGGL((k_track_grp<N, G, float>), dim3(blocks), dim3(64 * wpb), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_track_grp<N, G, double>), dim3(blocks), dim3(64 * wpb), 0, st, a);
+    const dim3 grid(blocks), block(64 * wpb);
+    if (a.coef0) {
+        if (fp32) hipLaunchKernelGGL((k_track_grp<N, G, float, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_track_grp<N, G, double, true>), grid, block, 0, st, a);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_track_grp<N, G, float, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_track_grp<N, G, double, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 

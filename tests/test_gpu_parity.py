@@ -260,3 +260,35 @@ def test_bad_layout_option(hc, ctx):
         ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=4))  # 4 lanes < 6 rows
     with pytest.raises(hc.HcError):
         ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=3))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_parameter_homotopy(hc, ctx, n, precision):
+    """Coefficients interpolated from a solved start instance to two targets
+    (section 6): the endpoints are the targets' roots, as the oracle's linear
+    homotopy and the total-degree solve of the targets both find."""
+    S, coef, gam = hc_inputs.dense_quadratic_instances(n, 3, seed=3000 + n)
+    td = ctx.load_system(S)
+    ep0, st0, _ = ctx.track(td, coef[:1], gam[:1])
+    assert (st0 == hc.HC_T_SUCCESS).all()
+    starts = ep0[0]
+    ps = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    ep, st, info = ctx.track(ps, coef[1:], start=starts, p_start=coef[0],
+                             opts=hc.default_opts(precision=precision))
+    oep, ost, _ = oracle.track(S, coef[1:], start=starts, coef0=coef[0], kind=oracle.LINEAR)
+    tep, tst, _ = ctx.track(td, coef[1:], gam[1:])
+    for i in range(2):
+        check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
+        check_instance_parity(ep[i], st[i], tep[i], tst[i], hc)
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
+
+
+def test_parameter_homotopy_needs_start(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(4, 2, seed=3100)
+    ps = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    with pytest.raises(hc.HcError):
+        ctx.track(ps, coef[1:], n_start=4)                      # no start points
+    with pytest.raises(hc.HcError):
+        ctx.track(ps, coef[1:], start=np.ones((4, 4)), p_start=coef[0],
+                  opts=hc.default_opts(lanes_per_path=1))    # layout without the blend
