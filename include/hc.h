@@ -129,6 +129,11 @@ typedef struct {
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
     int32_t lanes_per_path;   /* 1: one path per lane; 4 or 8: one row of [H_x | rhs]
                                  per lane, 4 or 8 lanes per path; 0 = autotuned  (0)     */
+    int32_t use_graph;        /* hc_track_device: capture the launch sequence in a
+                                 hipGraph on the first call and replay it while the
+                                 arguments stay the same (needs a non-null stream,
+                                 steps_per_launch 0, profiling off)             (0)     */
+    int32_t reserved;
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;
@@ -201,6 +206,46 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
                           const hc_c64 *gamma, const hc_opts *opts,
                           hc_c64 *endpoints, int32_t *status, hc_track_info *info,
                           void *stream);
+
+/* One job of a batch: a loaded system, its start points and instances, and its
+ * output buffers, with the meaning and layout of the hc_track arguments.  All
+ * pointers are device pointers. */
+typedef struct {
+    const hc_system *sys;
+    const hc_c64 *start;      /* [n_start][n] or NULL (total degree)          */
+    int32_t n_start;
+    int32_t n_inst;
+    const hc_c64 *p_start;    /* [n_params] (HC_PARAMETER) or NULL           */
+    const hc_c64 *p_target;   /* [n_inst][n_params]                          */
+    const hc_c64 *gamma;      /* [n_inst] or NULL                            */
+    hc_c64 *endpoints;        /* [n_inst][n_start][n]                        */
+    int32_t *status;          /* [n_inst][n_start]                           */
+    hc_track_info *info;      /* [n_inst][n_start] or NULL                   */
+} hc_job;
+
+/* Tracks every path of n_jobs jobs that may differ in system, n (2..8), kind,
+ * path count and instance count, with one persistent kernel per precision pass
+ * and homotopy kind: its wavefronts pop work items (job, instance, range of
+ * paths) from a device queue until it is empty, larger n first.  Options are
+ * shared (opts->steps_per_launch must be 0; the layout is lanes_per_path 0).
+ * Enqueued on `stream`; outputs valid after the stream is synchronised.  Each
+ * job's results equal those of hc_track_device on that job alone.
+ * Errors: HC_E_INVALID, HC_E_UNSUPPORTED (n = 1, steps_per_launch > 0,
+ * lanes_per_path = 1), HC_E_OOM, HC_E_DEVICE. */
+hc_status hc_track_batch_device(hc_ctx *ctx, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts,
+                                void *stream);
+
+/* Autotuner: runs hc_track_device with each candidate work decomposition
+ * (lanes per path, paths per wavefront work item) on these inputs, times it with
+ * HIP events on `stream`, and writes the fastest into *best (other fields copied
+ * from opts).  The choice is remembered in the context and used by later calls
+ * with tracks_per_item = lanes_per_path = 0 on the same (system, precision,
+ * n_start, n_inst).  The output buffers hold the last trial's results.
+ * Errors: as hc_track_device. */
+hc_status hc_autotune(hc_ctx *ctx, const hc_system *sys, const hc_c64 *start, int32_t n_start,
+                      const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma,
+                      const hc_opts *opts, hc_c64 *endpoints, int32_t *status, hc_track_info *info,
+                      void *stream, hc_opts *best);
 
 /* Event timings of the last hc_track / hc_track_device call on a context with
  * profiling switched on.  The times come from HIP events recorded on the stream

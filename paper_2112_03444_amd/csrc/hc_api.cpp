@@ -42,13 +42,16 @@ hc_status fail(hc_status code, const char *fmt, ...)
                         #call, hipGetErrorString(e_), __FILE__, __LINE__);                 \
     } while (0)
 
-// A grow-only device buffer.
+// A grow-only device buffer; `moves` counts reallocations (captured graphs and
+// other holders of its address must notice when it moves).
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    unsigned long long moves = 0;
     hipError_t ensure(size_t bytes)
     {
         if (bytes <= cap) return hipSuccess;
+        moves++;
         if (p) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess) return e;
@@ -101,6 +104,17 @@ struct hc_ctx {
     DevBuf coef;    // per-instance kernel tables (FP64 then FP32)
     DevBuf io;      // device copies of host inputs/outputs for hc_track
     DevBuf counter; // suspended-path counter, then two stage counters (profiling)
+    DevBuf queue;   // batch: per-pass job descriptors, work items, queue heads
+    std::vector<TrackArgs> h_jobs;   // host copies kept alive across the async uploads
+    std::vector<QueueItem> h_items;
+    // workspace generation: bumped whenever a buffer moves (captured graphs hold pointers)
+    unsigned long long generation = 0;
+    // hipGraph of the last hc_track_device call with use_graph, and its arguments
+    bool graph_valid = false;
+    std::vector<unsigned char> graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    // autotuner choices: key -> (lanes_per_path, tracks_per_item)
+    std::vector<std::pair<std::vector<unsigned char>, std::pair<int, int>>> tune;
     // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
     bool profiling = false;
     bool profiled_call = false;
@@ -184,6 +198,8 @@ void hc_destroy(hc_ctx *c)
     c->coef.release();
     c->io.release();
     c->counter.release();
+    c->queue.release();
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     for (hipEvent_t &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -320,6 +336,7 @@ hc_status hc_free_system(hc_ctx *c, hc_system *s)
     free_system_tables(s);
     delete s;
     c->systems.erase(it);
+    c->graph_valid = false;
     return HC_OK;
 }
 
@@ -396,6 +413,23 @@ static int choose_tracks_per_item(const hc_opts &o, int n_start, int lanes)
     return std::min(n_start, lanes == 1 ? 64 : 8 * slots);
 }
 
+template <typename T>
+static void put(std::vector<unsigned char> &k, const T &v)
+{
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&v);
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+static std::vector<unsigned char> tune_key(const hc_system *s, int precision, int n_start, int n_inst)
+{
+    std::vector<unsigned char> k;
+    put(k, s);
+    put(k, precision);
+    put(k, n_start);
+    put(k, n_inst);
+    return k;
+}
+
 static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                                    const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
                                    const hc_c64 *gamma, const hc_opts *opts_in, hc_c64 *endpoints,
@@ -408,6 +442,14 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     else hc_default_opts(&o);
     hc_status rc = check_opts(o);
     if (rc != HC_OK) return rc;
+    if (o.lanes_per_path == 0 && o.tracks_per_item == 0) {
+        const std::vector<unsigned char> k = tune_key(s, o.precision, n_start, n_inst);
+        for (auto &e : c->tune)
+            if (e.first == k) {
+                o.lanes_per_path = e.second.first;
+                o.tracks_per_item = e.second.second;
+            }
+    }
     const bool param = s->kind == HC_PARAMETER;
     if (!param && !start && n_start > s->bezout)
         return fail(HC_E_INVALID, "hc_track: n_start = %d exceeds the Bezout number %lld", n_start,
@@ -513,6 +555,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     TrackArgs ta;
     ta.gamma = reinterpret_cast<const double *>(gamma);
     ta.deg2 = s->deg2;
+    ta.n = n;
     ta.n_start = n_start;
     ta.items_per_inst = per_inst;
     ta.tracks_per_item = tpi;
@@ -595,8 +638,127 @@ hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, in
                           hc_track_info *info, void *stream)
 {
     g_err.clear();
-    return track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, opts, endpoints,
-                             status, info, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool graph = c && opts && opts->use_graph && st != nullptr && opts->steps_per_launch == 0 &&
+                       !c->profiling;
+    auto run = [&]() {
+        return track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, opts, endpoints, status,
+                                 info, st);
+    };
+    if (!graph) return run();
+    auto key = [&]() {
+        std::vector<unsigned char> k;
+        put(k, s);
+        put(k, start);
+        put(k, n_start);
+        put(k, p_start);
+        put(k, p_target);
+        put(k, n_inst);
+        put(k, gamma);
+        put(k, *opts);
+        put(k, endpoints);
+        put(k, status);
+        put(k, info);
+        put(k, st);
+        put(k, c->state.moves);
+        put(k, c->coef.moves);
+        put(k, c->counter.moves);
+        return k;
+    };
+    if (c->graph_valid && key() == c->graph_key) {
+        HIP_TRY(hipGraphLaunch(c->graph_exec, st));
+        return HC_OK;
+    }
+    // First call with these arguments: run it (this also sizes the workspace),
+    // then record the same launch sequence for replays.
+    hc_status rc = run();
+    if (rc != HC_OK) return rc;
+    c->graph_valid = false;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = run();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != HC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(HC_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (c->graph_exec) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_exec = nullptr;
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(HC_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    c->graph_key = key();
+    c->graph_valid = true;
+    return HC_OK;
+}
+
+hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start, const hc_c64 *p_start,
+                      const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma, const hc_opts *opts,
+                      hc_c64 *endpoints, int32_t *status, hc_track_info *info, void *stream, hc_opts *best)
+{
+    g_err.clear();
+    if (!c || !s || !best) return fail(HC_E_INVALID, "hc_autotune: NULL argument");
+    hc_opts o;
+    if (opts) o = *opts;
+    else hc_default_opts(&o);
+    o.use_graph = 0;
+    o.steps_per_launch = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(c->device));
+    // candidates: lanes per path x paths per lane group (or per lane)
+    std::vector<std::pair<int, int>> cand;
+    if (s->n >= 2) {
+        const int g = group_lanes(s->n);
+        for (int per_group : {2, 4, 8, 16}) cand.push_back({g, per_group * (64 / g)});
+    }
+    if (s->kind == HC_TOTAL_DEGREE)
+        for (int tpi : {64, 128, 256}) cand.push_back({1, tpi});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 0.0f;
+    std::pair<int, int> pick = {0, 0};
+    hc_status rc = HC_OK;
+    for (auto &cd : cand) {
+        hc_opts t = o;
+        t.lanes_per_path = cd.first;
+        t.tracks_per_item = std::max(1, std::min(cd.second, std::max(n_start, 1)));
+        rc = track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, &t, endpoints, status,
+                               info, st);
+        if (rc != HC_OK) break;
+        HIP_TRY(hipEventRecord(e0, st));
+        rc = track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, &t, endpoints, status,
+                               info, st);
+        if (rc != HC_OK) break;
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (pick.first == 0 || ms < best_ms) {
+            best_ms = ms;
+            pick = {cd.first, t.tracks_per_item};
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != HC_OK) return rc;
+    if (pick.first == 0) return fail(HC_E_UNSUPPORTED, "hc_autotune: no candidate applies to this system");
+    const std::vector<unsigned char> k = tune_key(s, o.precision, n_start, n_inst);
+    bool found = false;
+    for (auto &e : c->tune)
+        if (e.first == k) {
+            e.second = pick;
+            found = true;
+        }
+    if (!found) c->tune.push_back({k, pick});
+    *best = o;
+    if (opts) best->use_graph = opts->use_graph;
+    best->lanes_per_path = pick.first;
+    best->tracks_per_item = pick.second;
+    return HC_OK;
 }
 
 hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
@@ -653,6 +815,227 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     HIP_TRY(hipMemcpyAsync(status, d_st, b_st, hipMemcpyDeviceToHost, st));
     if (b_inf) HIP_TRY(hipMemcpyAsync(info, d_inf, b_inf, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return HC_OK;
+}
+
+hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts_in,
+                                void *stream)
+{
+    g_err.clear();
+    if (!c || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(HC_E_INVALID, "hc_track_batch_device: bad arguments");
+    hc_opts o;
+    if (opts_in) o = *opts_in;
+    else hc_default_opts(&o);
+    hc_status rc = check_opts(o);
+    if (rc != HC_OK) return rc;
+    if (o.steps_per_launch != 0 || o.lanes_per_path == 1)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: needs steps_per_launch = 0 and lanes_per_path 0/4/8");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool mixed = o.precision == HC_MIXED;
+
+    // per-job sizes and workspace offsets
+    struct Plan {
+        const hc_job *j;
+        const hc_system *s;
+        long long total;
+        int n, T, n_slots, n_tab, tpi;
+        bool param;
+        size_t st_off, tab64_off, tab32_off;
+    };
+    std::vector<Plan> plan;
+    size_t st_bytes = 0, tab_bytes = 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    for (int k = 0; k < n_jobs; k++) {
+        const hc_job &j = jobs[k];
+        if (!j.sys) return fail(HC_E_INVALID, "hc_track_batch_device: job %d has no system", k);
+        const hc_system *s = j.sys;
+        if (std::find(c->systems.begin(), c->systems.end(), s) == c->systems.end())
+            return fail(HC_E_INVALID, "hc_track_batch_device: job %d's system is not loaded in this context", k);
+        if (j.n_start < 0 || j.n_inst < 0) return fail(HC_E_INVALID, "hc_track_batch_device: job %d negative size", k);
+        if (s->n < 2) return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: job %d has n = 1", k);
+        Plan p{};
+        p.j = &j;
+        p.s = s;
+        p.n = s->n;
+        p.T = s->T;
+        p.n_slots = s->n * s->T;
+        p.param = s->kind == HC_PARAMETER;
+        p.total = (long long)j.n_start * j.n_inst;
+        if (p.total > 0) {
+            if (!p.param && !j.start && j.n_start > s->bezout)
+                return fail(HC_E_INVALID, "hc_track_batch_device: job %d n_start exceeds the Bezout number", k);
+            if (p.param && (!j.start || (!j.p_start && s->n_params > 0)))
+                return fail(HC_E_INVALID, "hc_track_batch_device: job %d needs start points and p_start", k);
+            if (!j.endpoints || !j.status || (!j.p_target && s->n_params > 0))
+                return fail(HC_E_INVALID, "hc_track_batch_device: job %d has a NULL buffer", k);
+        }
+        p.n_tab = j.n_inst + (p.param ? 1 : 0);
+        p.tpi = choose_tracks_per_item(o, j.n_start, group_lanes(p.n));
+        p.st_off = st_bytes;
+        st_bytes += al((size_t)p.total * ((2 * p.n + 2) * 8 + 6 * 4));
+        p.tab64_off = tab_bytes;
+        tab_bytes += al((size_t)p.n_tab * p.n_slots * 16);
+        p.tab32_off = tab_bytes;
+        if (mixed) tab_bytes += al((size_t)p.n_tab * p.n_slots * 8);
+        plan.push_back(p);
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(c->state.ensure(st_bytes));
+    HIP_TRY(c->coef.ensure(tab_bytes));
+    HIP_TRY(c->counter.ensure(64));
+    unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(static_cast<char *>(c->counter.p) + 16);
+
+    // job descriptors (one set per pass) and the two queues (total degree, parameter)
+    c->h_jobs.assign((size_t)2 * n_jobs, TrackArgs{});
+    std::vector<QueueItem> q_td, q_par;
+    std::vector<int> job_n(n_jobs);
+    for (int k = 0; k < n_jobs; k++) {
+        Plan &p = plan[k];
+        job_n[k] = p.n;
+        char *sb = static_cast<char *>(c->state.p) + p.st_off;
+        TrackState S;
+        double *dp = reinterpret_cast<double *>(sb);
+        S.xr = dp;
+        S.xi = dp + (size_t)p.total * p.n;
+        S.t = dp + (size_t)p.total * 2 * p.n;
+        S.h = S.t + p.total;
+        int *ip = reinterpret_cast<int *>(dp + (size_t)p.total * (2 * p.n + 2));
+        S.succ = ip;
+        S.steps = ip + p.total;
+        S.rejects = ip + 2 * p.total;
+        S.nits = ip + 3 * p.total;
+        S.status = ip + 4 * p.total;
+        S.escal = ip + 5 * p.total;
+        double *t64 = reinterpret_cast<double *>(static_cast<char *>(c->coef.p) + p.tab64_off);
+        float *t32 = mixed ? reinterpret_cast<float *>(static_cast<char *>(c->coef.p) + p.tab32_off) : nullptr;
+        const double *t64s = p.param ? t64 + (size_t)p.j->n_inst * p.n_slots * 2 : nullptr;
+        const float *t32s = (p.param && t32) ? t32 + (size_t)p.j->n_inst * p.n_slots * 2 : nullptr;
+        if (p.total == 0) continue;
+
+        PrepArgs pa;
+        pa.n = p.n;
+        pa.T = p.T;
+        pa.n_inst = p.j->n_inst;
+        pa.n_params = p.s->n_params;
+        pa.n_slots = p.n_slots;
+        pa.slot_ptr = p.s->d_slot_ptr;
+        pa.slot_term = p.s->d_slot_term;
+        pa.slot_mult = p.s->d_slot_mult;
+        pa.term_const = p.s->d_term_const;
+        pa.map_ptr = p.s->d_map_ptr;
+        pa.map_col = p.s->d_map_col;
+        pa.map_val = p.s->d_map_val;
+        pa.params = reinterpret_cast<const double *>(p.j->p_target);
+        pa.out64 = t64;
+        pa.out32 = t32;
+        HIP_TRY(launch_prep(pa, st));
+        if (p.param) {
+            PrepArgs p0 = pa;
+            p0.n_inst = 1;
+            p0.params = reinterpret_cast<const double *>(p.j->p_start);
+            p0.out64 = const_cast<double *>(t64s);
+            p0.out32 = const_cast<float *>(t32s);
+            HIP_TRY(launch_prep(p0, st));
+        }
+        InitArgs ia;
+        ia.n = p.n;
+        ia.n_start = p.j->n_start;
+        ia.total = p.total;
+        ia.deg2 = p.s->deg2;
+        ia.start = reinterpret_cast<const double *>(p.j->start);
+        ia.h0 = o.h0;
+        ia.s = S;
+        HIP_TRY(launch_init(ia, st));
+
+        for (int pass = 0; pass < 2; pass++) {
+            const bool fp32 = pass == 0;
+            TrackArgs &ta = c->h_jobs[(size_t)pass * n_jobs + k];
+            ta.n = p.n;
+            ta.coef = fp32 ? (const void *)t32 : (const void *)t64;
+            ta.coef0 = !p.param ? nullptr : fp32 ? (const void *)t32s : (const void *)t64s;
+            ta.gamma = reinterpret_cast<const double *>(p.j->gamma);
+            ta.deg2 = p.s->deg2;
+            ta.n_start = p.j->n_start;
+            ta.tracks_per_item = p.tpi;
+            ta.items_per_inst = (p.j->n_start + p.tpi - 1) / p.tpi;
+            ta.n_items = ta.items_per_inst * p.j->n_inst;
+            ta.total = p.total;
+            ta.t_final = fp32 ? 1.0 - o.t_end : 1.0;
+            ta.launch_steps = 0;
+            ta.escalate = fp32 ? 1 : 0;
+            ta.h0 = o.h0;
+            ta.h_min = o.h_min;
+            ta.h_max = o.h_max;
+            ta.beta_inc = o.beta_inc;
+            ta.beta_dec = o.beta_dec;
+            ta.tau = fp32 ? o.tau32 : o.tau64;
+            ta.pred_tol = o.pred_tol;
+            ta.inf2 = o.inf_bound * o.inf_bound;
+            ta.n_inc = o.n_inc;
+            ta.max_newton = o.max_newton;
+            ta.max_steps = o.max_steps;
+            ta.s = S;
+            ta.n_suspended = static_cast<unsigned *>(c->counter.p);
+            ta.stage_count = c->profiling ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
+        }
+        std::vector<QueueItem> &q = p.param ? q_par : q_td;
+        for (int i = 0; i < p.j->n_inst; i++)
+            for (int tb = 0; tb < p.j->n_start; tb += p.tpi)
+                q.push_back({k, i, tb, std::min(tb + p.tpi, p.j->n_start)});
+    }
+    // larger systems first: their items are the longest
+    auto by_n = [&](const QueueItem &x, const QueueItem &y) { return job_n[x.job] > job_n[y.job]; };
+    std::stable_sort(q_td.begin(), q_td.end(), by_n);
+    std::stable_sort(q_par.begin(), q_par.end(), by_n);
+    c->h_items = q_td;
+    c->h_items.insert(c->h_items.end(), q_par.begin(), q_par.end());
+    const size_t b_jobs = al(c->h_jobs.size() * sizeof(TrackArgs));
+    const size_t b_items = al(std::max<size_t>(c->h_items.size(), 1) * sizeof(QueueItem));
+    HIP_TRY(c->queue.ensure(b_jobs + b_items + 256));
+    char *qb = static_cast<char *>(c->queue.p);
+    TrackArgs *d_jobs = reinterpret_cast<TrackArgs *>(qb);
+    QueueItem *d_items = reinterpret_cast<QueueItem *>(qb + b_jobs);
+    unsigned *heads = reinterpret_cast<unsigned *>(qb + b_jobs + b_items);
+    if (n_jobs > 0)
+        HIP_TRY(hipMemcpyAsync(d_jobs, c->h_jobs.data(), c->h_jobs.size() * sizeof(TrackArgs), hipMemcpyHostToDevice, st));
+    if (!c->h_items.empty())
+        HIP_TRY(hipMemcpyAsync(d_items, c->h_items.data(), c->h_items.size() * sizeof(QueueItem),
+                               hipMemcpyHostToDevice, st));
+    const int n_td = (int)q_td.size(), n_par = (int)q_par.size();
+    auto run_pass = [&](bool fp32) -> hc_status {
+        const TrackArgs *pj = d_jobs + (fp32 ? 0 : n_jobs);
+        HIP_TRY(launch_fill_u32(heads, 0u, 2, st));
+        if (n_td) HIP_TRY(launch_track_queue(fp32, false, pj, d_items, n_td, heads, queue_waves(fp32, false), st));
+        if (n_par)
+            HIP_TRY(launch_track_queue(fp32, true, pj, d_items + n_td, n_par, heads + 1, queue_waves(fp32, true), st));
+        return HC_OK;
+    };
+    if (mixed) {
+        rc = run_pass(true);
+        if (rc != HC_OK) return rc;
+    }
+    rc = run_pass(false);
+    if (rc != HC_OK) return rc;
+    for (int k = 0; k < n_jobs; k++) {
+        const Plan &p = plan[k];
+        if (p.total == 0) continue;
+        const TrackArgs &ta = c->h_jobs[(size_t)n_jobs + k];
+        RefineArgs ra;
+        ra.coef = static_cast<const double *>(ta.coef);
+        ra.gamma = ta.gamma;
+        ra.deg2 = p.s->deg2;
+        ra.n_start = p.j->n_start;
+        ra.total = p.total;
+        ra.max_refine = o.max_refine;
+        ra.tau_refine = o.tau_refine;
+        ra.inf2 = o.inf_bound * o.inf_bound;
+        ra.eta_max = o.eta_max;
+        ra.s = ta.s;
+        ra.endpoints = reinterpret_cast<double *>(p.j->endpoints);
+        ra.status = p.j->status;
+        ra.info = p.j->info;
+        HIP_TRY(launch_refine(p.n, ra, st));
+    }
     return HC_OK;
 }
 

@@ -60,6 +60,7 @@ struct InitArgs {
 };
 
 struct TrackArgs {
+    int n;                    // unknowns (the persistent tracker dispatches on it)
     const void *coef;         // [n_inst][n][T][2] in the tracking precision
     const void *coef0;        // parameter homotopy: start tables [n][T][2], else null
     const double *gamma;      // [n_inst][2] or null (gamma = 1)
@@ -94,6 +95,22 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);
 // fp32 selects the complex-FP32 tracker, else complex FP64.
 hipError_t launch_track(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
+// One entry of the persistent tracker's device work queue.
+struct QueueItem {
+    int job;   // index into the jobs' TrackArgs
+    int inst;  // instance within the job
+    int tb;    // first path
+    int tend;  // one past the last path
+};
+
+// Persistent tracker over a work queue (group layout, n in 2..8): n_waves
+// wavefronts pop items by atomicAdd on *head (zeroed by the caller).
+hipError_t launch_track_queue(bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items, int n_items,
+                              unsigned *head, int n_waves, hipStream_t st);
+int queue_waves(bool fp32, bool param);
+// Sets count 32-bit words to value (graph-safe replacement for hipMemsetAsync).
+hipError_t launch_fill_u32(unsigned *p, unsigned value, int count, hipStream_t st);
+
 // G lanes per path (one row of [H_x | rhs] per lane); G = group_lanes(n).
 hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
 int group_lanes(int n);

@@ -592,6 +592,19 @@ __global__ __launch_bounds__(256) void k_refine(const RefineArgs a)
 
 // ---------------------------------------------------------------- launchers
 
+__global__ void k_fill_u32(unsigned *p, unsigned value, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = value;
+}
+
+hipError_t launch_fill_u32(unsigned *p, unsigned value, int count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((count + 255) / 256), dim3(256), 0, st, p, value, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const PrepArgs &a, hipStream_t st)
 {
     const long long n = (long long)a.n_inst * a.n_slots;

@@ -218,8 +218,11 @@ __device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base
 
 }  // namespace
 
+// Tracks the paths tb .. tend-1 of instance `inst` with the wavefront's lane
+// groups until every one of them has ended or been suspended.  Called with the
+// whole wavefront active and wavefront-uniform arguments.
 template <int N, int G, typename R, bool PARAM>
-__global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
+__device__ __forceinline__ void run_item(const TrackArgs &a, const int inst, const int tb, const int tend)
 {
     static_assert(G == 4 || G == 8 || G == 16, "group size");
     static_assert(N <= G, "one row per lane");
@@ -228,13 +231,6 @@ __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
     const int lane = threadIdx.x & 63;
     const int r = lane & (G - 1);
     const int base = lane - r;
-    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = blockDim.x >> 6;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + wib);
-    if (item >= a.n_items) return;
-    const int inst = item / a.items_per_inst;
-    const int tb = (item - inst * a.items_per_inst) * a.tracks_per_item;
-    const int tend = min(tb + a.tracks_per_item, a.n_start);
     cx<R> gam = {R(1), R(0)};
     if (a.gamma) gam = {R(a.gamma[2 * inst]), R(a.gamma[2 * inst + 1])};
     const long long gbase = (long long)inst * a.n_start;
@@ -461,6 +457,83 @@ __global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
         }
         refill();
     }
+}
+
+// One work item per wavefront, items in block order (XCD-aware).
+template <int N, int G, typename R, bool PARAM>
+__global__ __launch_bounds__(256) void k_track_grp(const TrackArgs a)
+{
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = blockDim.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * wpb + wib);
+    if (item >= a.n_items) return;
+    const int inst = item / a.items_per_inst;
+    const int tb = (item - inst * a.items_per_inst) * a.tracks_per_item;
+    const int tend = min(tb + a.tracks_per_item, a.n_start);
+    run_item<N, G, R, PARAM>(a, inst, tb, tend);
+}
+
+// Persistent tracker over a device work queue: each wavefront pops work items
+// (job, instance, path range) with one atomic until the queue is empty and runs
+// them with the code for the item's n.  Jobs may differ in n, kind-matching
+// PARAM, path count and instance count.  Every wavefront leaves once the queue
+// head passes n_items, so the grid always drains.
+template <typename R, bool PARAM>
+__global__ __launch_bounds__(256, (sizeof(R) == 4 && !PARAM) ? 2 : 1) void k_track_queue(const TrackArgs *__restrict__ jobs,
+                                                     const QueueItem *__restrict__ items, int n_items,
+                                                     unsigned *head)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned got = 0;
+        if (lane == 0) got = atomicAdd(head, 1u);
+        const int idx = (int)__builtin_amdgcn_readfirstlane(got);
+        if (idx >= n_items) break;
+        const QueueItem it = items[idx];
+        const TrackArgs a = jobs[it.job];
+        switch (a.n) {
+        case 2: run_item<2, 4, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 3: run_item<3, 4, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 4: run_item<4, 4, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 5: run_item<5, 8, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 6: run_item<6, 8, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 7: run_item<7, 8, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        case 8: run_item<8, 8, R, PARAM>(a, it.inst, it.tb, it.tend); break;
+        default: break;
+        }
+    }
+}
+
+hipError_t launch_track_queue(bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items, int n_items,
+                              unsigned *head, int n_waves, hipStream_t st)
+{
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid((n_waves + 3) / 4), block(256);
+    if (param) {
+        if (fp32) hipLaunchKernelGGL((k_track_queue<float, true>), grid, block, 0, st, jobs, items, n_items, head);
+        else hipLaunchKernelGGL((k_track_queue<double, true>), grid, block, 0, st, jobs, items, n_items, head);
+    } else {
+        if (fp32) hipLaunchKernelGGL((k_track_queue<float, false>), grid, block, 0, st, jobs, items, n_items, head);
+        else hipLaunchKernelGGL((k_track_queue<double, false>), grid, block, 0, st, jobs, items, n_items, head);
+    }
+    return hipGetLastError();
+}
+
+// Resident wavefronts of the persistent tracker on this device (all CUs).
+int queue_waves(bool fp32, bool param)
+{
+    int dev = 0, cus = 0, blocks = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e;
+    if (param)
+        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_track_queue<float, true>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_track_queue<double, true>, 256, 0);
+    else
+        e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_track_queue<float, false>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_track_queue<double, false>, 256, 0);
+    if (e != hipSuccess || blocks < 1) blocks = 1;
+    return cus * blocks * 4;
 }
 
 template <int N, int G>

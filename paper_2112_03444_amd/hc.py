@@ -45,7 +45,14 @@ class Opts(ctypes.Structure):
                  "tau_refine", "inf_bound", "eta_max", "t_end")] + \
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
-                 "steps_per_launch", "tracks_per_item", "lanes_per_path")]
+                 "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "reserved")]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("sys", ctypes.c_void_p), ("start", ctypes.c_void_p), ("n_start", ctypes.c_int32),
+                ("n_inst", ctypes.c_int32), ("p_start", ctypes.c_void_p), ("p_target", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p), ("endpoints", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
 
 
 class Profile(ctypes.Structure):
@@ -102,6 +109,11 @@ def lib():
         L.hc_track.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P]
         L.hc_track_device.restype = ctypes.c_int
         L.hc_track_device.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P]
+        L.hc_autotune.restype = ctypes.c_int
+        L.hc_autotune.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P,
+                                  ctypes.POINTER(Opts)]
+        L.hc_track_batch_device.restype = ctypes.c_int
+        L.hc_track_batch_device.argtypes = [P, I32, ctypes.POINTER(Job), ctypes.POINTER(Opts), P]
         L.hc_set_profiling.restype = ctypes.c_int
         L.hc_set_profiling.argtypes = [P, I32]
         L.hc_last_profile.restype = ctypes.c_int
@@ -279,3 +291,48 @@ class Context:
         _check(lib().hc_track_device(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target),
                                      n_inst, dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
                                      ctypes.c_void_p(stream.cuda_stream)))
+
+    def autotune(self, s: System, p_target, gamma, endpoints, status, info=None, start=None, p_start=None,
+                 n_start: Optional[int] = None, opts: Optional[Opts] = None, stream=None) -> Opts:
+        """hc_autotune on torch tensors; returns the chosen options."""
+        import torch
+
+        def dp(t):
+            return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+        n_inst = p_target.shape[0]
+        if n_start is None:
+            n_start = s.bezout if start is None else start.shape[0]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o = opts if opts is not None else default_opts()
+        best = Opts()
+        _check(lib().hc_autotune(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target), n_inst,
+                                 dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
+                                 ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best)))
+        return best
+
+    def track_batch_device(self, jobs, opts: Optional[Opts] = None, stream=None):
+        """hc_track_batch_device.  jobs: list of dicts with keys sys (System),
+        p_target, endpoints, status and optionally gamma, info, start, p_start,
+        n_start (torch tensors on the device, as in track_device)."""
+        import torch
+
+        def dp(t):
+            return None if t is None else t.data_ptr()
+
+        arr = (Job * max(len(jobs), 1))()
+        for k, j in enumerate(jobs):
+            s = j["sys"]
+            start = j.get("start")
+            n_start = j.get("n_start")
+            if n_start is None:
+                n_start = s.bezout if start is None else start.shape[0]
+            arr[k] = Job(s.handle.value if hasattr(s.handle, "value") else s.handle, dp(start), n_start,
+                         j["p_target"].shape[0], dp(j.get("p_start")), dp(j["p_target"]), dp(j.get("gamma")),
+                         dp(j["endpoints"]), dp(j["status"]), dp(j.get("info")))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        o = opts if opts is not None else default_opts()
+        _check(lib().hc_track_batch_device(self.handle, len(jobs), arr, ctypes.byref(o),
+                                           ctypes.c_void_p(stream.cuda_stream)))

@@ -292,3 +292,112 @@ def test_parameter_homotopy_needs_start(hc, ctx):
     with pytest.raises(hc.HcError):
         ctx.track(ps, coef[1:], start=np.ones((4, 4)), p_start=coef[0],
                   opts=hc.default_opts(lanes_per_path=1))    # layout without the blend
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_of_uneven_jobs_equals_single_calls(hc, ctx, precision):
+    """One persistent-kernel batch over jobs of different n, kind, path and
+    instance counts returns, job by job, what a call on that job alone returns."""
+    import torch
+    dev = torch.device("cuda:0")
+    opts = hc.default_opts(precision=precision)
+    specs = [(3, 2, None, 11), (5, 3, 20, 12), (8, 4, None, 13), (6, 1, 50, 14), (2, 5, None, 15)]
+    jobs, refs = [], []
+    for n, n_inst, n_start, seed in specs:
+        S, coef, gam = hc_inputs.dense_quadratic_instances(n, n_inst, seed=seed)
+        sysh = ctx.load_system(S)
+        ns = n_start if n_start is not None else sysh.bezout
+        p = torch.from_numpy(coef).to(dev)
+        g = torch.from_numpy(gam).to(dev)
+        ref = [torch.empty((n_inst, ns, n), dtype=torch.complex128, device=dev),
+               torch.empty((n_inst, ns), dtype=torch.int32, device=dev),
+               torch.empty((n_inst, ns, 32), dtype=torch.uint8, device=dev)]
+        ctx.track_device(sysh, p, g, ref[0], ref[1], ref[2], n_start=ns, opts=opts)
+        torch.cuda.synchronize()
+        refs.append([r.cpu().numpy() for r in ref])
+        jobs.append(dict(sys=sysh, p_target=p, gamma=g, n_start=ns,
+                         endpoints=torch.zeros_like(ref[0]), status=torch.zeros_like(ref[1]),
+                         info=torch.zeros_like(ref[2])))
+    # a parameter-homotopy job: n = 4, start points from a solved instance
+    S, coef, gam = hc_inputs.dense_quadratic_instances(4, 3, seed=16)
+    td = ctx.load_system(S)
+    e0, s0, _ = ctx.track(td, coef[:1], gam[:1])
+    ps = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    st_pts = torch.from_numpy(np.ascontiguousarray(e0[0])).to(dev)
+    p = torch.from_numpy(coef[1:]).to(dev)
+    p0 = torch.from_numpy(coef[0]).to(dev)
+    ref = [torch.empty((2, 16, 4), dtype=torch.complex128, device=dev),
+           torch.empty((2, 16), dtype=torch.int32, device=dev),
+           torch.empty((2, 16, 32), dtype=torch.uint8, device=dev)]
+    ctx.track_device(ps, p, None, ref[0], ref[1], ref[2], start=st_pts, p_start=p0, opts=opts)
+    torch.cuda.synchronize()
+    refs.append([r.cpu().numpy() for r in ref])
+    jobs.append(dict(sys=ps, p_target=p, start=st_pts, p_start=p0, endpoints=torch.zeros_like(ref[0]),
+                     status=torch.zeros_like(ref[1]), info=torch.zeros_like(ref[2])))
+
+    ctx.track_batch_device(jobs, opts=opts)
+    torch.cuda.synchronize()
+    for j, r in zip(jobs, refs):
+        np.testing.assert_array_equal(j["endpoints"].cpu().numpy(), r[0])
+        np.testing.assert_array_equal(j["status"].cpu().numpy(), r[1])
+        np.testing.assert_array_equal(j["info"].cpu().numpy(), r[2])
+
+
+def test_batch_rejects_unsupported(hc, ctx):
+    import torch
+    S, coef, gam = hc_inputs.dense_quadratic_instances(1, 1, seed=17)
+    s1 = ctx.load_system(S)
+    dev = torch.device("cuda:0")
+    job = dict(sys=s1, p_target=torch.from_numpy(coef).to(dev),
+               endpoints=torch.zeros((1, 2, 1), dtype=torch.complex128, device=dev),
+               status=torch.zeros((1, 2), dtype=torch.int32, device=dev))
+    with pytest.raises(hc.HcError):
+        ctx.track_batch_device([job])  # n = 1 has no group layout
+    ctx.track_batch_device([])          # an empty batch is a no-op
+
+
+def test_graph_replay_matches_eager(hc, ctx):
+    """A captured launch sequence, replayed several times with eager work and
+    synchronisations in between and with the inputs changed in place, gives the
+    eager results every time."""
+    import torch
+    dev = torch.device("cuda:0")
+    S, coef, gam = hc_inputs.dense_quadratic_instances(6, 4, seed=91)
+    _, coef2, _ = hc_inputs.dense_quadratic_instances(6, 4, seed=92)
+    sysh = ctx.load_system(S)
+    stream = torch.cuda.Stream()
+    p = torch.from_numpy(coef).to(dev)
+    g = torch.from_numpy(gam).to(dev)
+    ep = torch.zeros((4, 64, 6), dtype=torch.complex128, device=dev)
+    st = torch.zeros((4, 64), dtype=torch.int32, device=dev)
+    for precision in ("mixed", "fp64"):
+        og = hc.default_opts(precision=precision, use_graph=1)
+        for rep in range(4):
+            src = coef if rep % 2 == 0 else coef2
+            p.copy_(torch.from_numpy(src))
+            torch.cuda.synchronize()
+            ctx.track_device(sysh, p, g, ep, st, None, opts=og, stream=stream)
+            stream.synchronize()
+            got = (ep.cpu().numpy(), st.cpu().numpy())
+            ep.zero_()                      # eager work between replays
+            ref = ctx.track(sysh, src, gam, opts=hc.default_opts(precision=precision))
+            np.testing.assert_array_equal(got[0], ref[0])
+            np.testing.assert_array_equal(got[1], ref[1])
+
+
+def test_autotune_choice_is_used_and_exact(hc, ctx):
+    import torch
+    dev = torch.device("cuda:0")
+    S, coef, gam = hc_inputs.dense_quadratic_instances(5, 8, seed=93)
+    sysh = ctx.load_system(S)
+    p = torch.from_numpy(coef).to(dev)
+    g = torch.from_numpy(gam).to(dev)
+    ep = torch.zeros((8, 32, 5), dtype=torch.complex128, device=dev)
+    st = torch.zeros((8, 32), dtype=torch.int32, device=dev)
+    best = ctx.autotune(sysh, p, g, ep, st, opts=hc.default_opts(precision="mixed"))
+    assert best.lanes_per_path in (1, 8) and best.tracks_per_item >= 1
+    explicit = ctx.track(sysh, coef, gam, opts=hc.default_opts(
+        precision="mixed", lanes_per_path=best.lanes_per_path, tracks_per_item=best.tracks_per_item))
+    auto = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed"))
+    for a, b in zip(explicit, auto):
+        np.testing.assert_array_equal(a, b)

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(hc):
 
 
 def test_struct_layouts_match_header(hc):
-    assert ctypes.sizeof(hc.Opts) == 12 * 8 + 8 * 4
+    assert ctypes.sizeof(hc.Opts) == 12 * 8 + 10 * 4
     assert hc.INFO_DTYPE.itemsize == 32
     assert ctypes.sizeof(hc.hc.SystemDesc) == 4 * 2 + 8 * 2 + 4 * 2 + 8 * 4
 
