@@ -78,7 +78,7 @@ def roofline(profs, n, kind):
     peak = PEAK_TFLOPS[key]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": f"k_track<8,{'float' if key == 'fp32' else 'double'}>",
+            "kernel": f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>",
             "kernel_ms_per_launch": round(per_launch_ms, 4), "launches_per_step": launches,
             "stages_per_launch": stages / launches, "flops_per_stage": w_stage(n)}
 
@@ -97,6 +97,48 @@ def cpu_baseline(S, coef, gam, budget_s=12.0):
     return {"value": round(paths / dt, 1), "unit": "tracks/s", "cores": threads, "kind": "oracle",
             "sample": f"first {k} of the 512 instances ({paths} paths, FP64), {dt:.1f} s, "
                       f"{threads} threads; success {np.mean(ost == 0):.4f}"}
+
+
+def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5):
+    """Open-loop Poisson arrivals at `rate` requests/s into the serving loop.
+    Mix: 60% one dense n = 8 system with 256 paths (the throughput workload's
+    request), 40% one dense system with n uniform in 5..8 and 2^n paths."""
+    import hc_inputs
+    rng = np.random.default_rng(seed)
+    systems = {n: ctx.load_system(hc_inputs.dense_quadratic_system(n)) for n in range(5, 9)}
+    pool = {n: hc_inputs.dense_quadratic_instances(n, 64, seed=900 + n) for n in range(5, 9)}
+    srv = hc.Server(ctx, max_inflight=3, max_batch_requests=64, opts=hc.default_opts(precision="mixed"))
+    total = warm_s + meas_s
+    gaps = rng.exponential(1.0 / rate, size=int(rate * total * 1.2) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < total]
+    kinds = rng.random(len(arrivals))
+    ns = rng.integers(5, 9, size=len(arrivals))
+    picks = rng.integers(0, 64, size=len(arrivals))
+    tickets = []
+    reset_done = False
+    t0 = time.perf_counter()
+    paths = 0
+    for k, ta in enumerate(arrivals):
+        n = 8 if kinds[k] < 0.6 else int(ns[k])
+        _, coef, gam = pool[n]
+        while time.perf_counter() - t0 < ta:
+            pass
+        if not reset_done and ta >= warm_s:
+            srv.reset_stats()
+            reset_done = True
+        tickets.append(srv.submit(systems[n], coef[picks[k]], gam[picks[k]]))
+        if ta >= warm_s:
+            paths += 2 ** n
+    for t in tickets:
+        srv.wait(t)
+    st = srv.stats()
+    srv.close()
+    return {"offered_rate": rate, "measured_s": meas_s, "requests": int(st["latencies"]),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+            "solves_per_s": round(st["completed"] / st["wall_s"], 1),
+            "tracks_per_s": round(st["tracks_completed"] / st["wall_s"], 1), "batches": int(st["batches"]),
+            "mix": "60% dense n=8 (256 paths), 40% dense n in 5..8 (2^n paths); mixed precision"}
 
 
 def main():
@@ -186,6 +228,24 @@ def main():
         extras["latency_dense3_single_ms"] = {"p50": float(np.percentile(lat, 50)),
                                               "p99": float(np.percentile(lat, 99)),
                                               "repeats": len(lat)}
+        # the same with the launch sequence replayed from a captured hipGraph
+        log("bench: single-instance latency with hipGraph replay, 1000 calls")
+        gs = torch.cuda.Stream()
+        og = hc.default_opts(precision="fp64", use_graph=1)
+        lat = []
+        for r in range(1050):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.track_device(sys1, p1, q1, e1, s1, None, opts=og, stream=gs)
+            gs.synchronize()
+            if r >= 50:
+                lat.append(time.perf_counter() - t0)
+        lat = np.array(lat) * 1e3
+        extras["latency_dense3_single_graph_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                                    "p99": float(np.percentile(lat, 99)),
+                                                    "repeats": len(lat)}
+        log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s")
+        extras["serving"] = serve_mix(ctx, hc)
 
     cpu = None
     if not args.no_cpu:

@@ -247,6 +247,73 @@ hc_status hc_autotune(hc_ctx *ctx, const hc_system *sys, const hc_c64 *start, in
                       const hc_opts *opts, hc_c64 *endpoints, int32_t *status, hc_track_info *info,
                       void *stream, hc_opts *best);
 
+/* ---- serving: continuous batching of solve requests (host buffers) ---------- */
+
+typedef struct hc_server hc_server;
+
+typedef struct {
+    int32_t max_inflight;       /* batches on the device at once, each with its own
+                                   stream and workspace                      (3)     */
+    int32_t max_batch_requests; /* requests per batch                        (64)    */
+    int64_t hbm_budget;         /* device bytes for the requests in flight   (8 GiB) */
+    hc_opts opts;               /* tracking options of every request (mixed precision) */
+} hc_server_opts;
+
+/* One solve request: the hc_track arguments in host memory.  Inputs are copied
+ * at submission; outputs are written when the request completes. */
+typedef struct {
+    const hc_system *sys;       /* loaded on the server's device (n >= 2)    */
+    int32_t n_start;
+    int32_t n_inst;
+    const hc_c64 *start;        /* [n_start][n] or NULL (total degree)      */
+    const hc_c64 *p_start;      /* [n_params] (HC_PARAMETER) or NULL        */
+    const hc_c64 *p_target;     /* [n_inst][n_params]                       */
+    const hc_c64 *gamma;        /* [n_inst] or NULL                         */
+    hc_c64 *endpoints;          /* [n_inst][n_start][n]                     */
+    int32_t *status;            /* [n_inst][n_start]                        */
+    hc_track_info *info;        /* [n_inst][n_start] or NULL                */
+} hc_request;
+
+typedef struct {
+    int64_t submitted, completed, batches, tracks_completed;
+    int64_t latencies;          /* completed requests submitted since the last reset */
+    int64_t peak_bytes;         /* largest device footprint admitted at once         */
+    double wall_s;              /* seconds since creation or the last reset          */
+    double mean_ms, p50_ms, p99_ms, max_ms;  /* submission -> completion latency     */
+} hc_server_stats;
+
+/* Fills *o with the defaults listed above. */
+void hc_server_default_opts(hc_server_opts *o);
+
+/* Starts a server on ctx's device: a dispatcher thread forms batches from the
+ * pending requests (first come first served, admitted while the device bytes of
+ * the batches in flight stay within hbm_budget; a request larger than the budget
+ * runs alone) and tracks each batch with hc_track_batch_device on a free slot, so
+ * batches overlap on the device; a completion thread copies results out.  A
+ * request's results equal those of tracking it alone.  The context must outlive
+ * the server.  Errors: HC_E_INVALID, HC_E_UNSUPPORTED (opts.steps_per_launch > 0
+ * or lanes_per_path = 1), HC_E_OOM, HC_E_DEVICE. */
+hc_status hc_server_create(hc_ctx *ctx, const hc_server_opts *opts, hc_server **out);
+
+/* Queues a request; *ticket identifies it.  Thread-safe.  The output buffers
+ * must stay valid until the request completes.  Errors: HC_E_INVALID,
+ * HC_E_UNSUPPORTED (n = 1), HC_E_OOM. */
+hc_status hc_server_submit(hc_server *srv, const hc_request *req, int64_t *ticket);
+
+/* *done = 1 once the request's outputs are written.  Returns the request's error
+ * if it failed.  Thread-safe. */
+hc_status hc_server_poll(hc_server *srv, int64_t ticket, int32_t *done);
+
+/* Blocks until the request completes, then forgets the ticket.  Thread-safe. */
+hc_status hc_server_wait(hc_server *srv, int64_t ticket);
+
+/* Counters and latency percentiles since creation or the last reset. */
+hc_status hc_server_get_stats(hc_server *srv, hc_server_stats *out);
+hc_status hc_server_reset_stats(hc_server *srv);
+
+/* Finishes every submitted request, stops the threads and frees the server. */
+hc_status hc_server_destroy(hc_server *srv);
+
 /* Event timings of the last hc_track / hc_track_device call on a context with
  * profiling switched on.  The times come from HIP events recorded on the stream
  * the kernels ran on; a "stage" is one evaluation of [H_x | rhs] plus one LU solve

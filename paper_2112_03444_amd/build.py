@@ -17,8 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhc.so")
-SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_kernels.hip"),
-           os.path.join(CSRC, "hc_track_group.hip")]
+SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp"),
+           os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip")]
 ARCH = "gfx950"
 
 
@@ -32,7 +32,7 @@ def hipcc() -> str:
 def compile_cmd(out: str):
     return [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-fPIC", "-shared", "-I", INCLUDE, "-I", CSRC, *SOURCES, "-o", out]
+            "-fPIC", "-shared", "-pthread", "-I", INCLUDE, "-I", CSRC, *SOURCES, "-o", out]
 
 
 def build(verbose: bool = False) -> str:

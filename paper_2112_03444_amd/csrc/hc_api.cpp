@@ -14,14 +14,15 @@
 #include <string>
 #include <vector>
 
-#include "hc.h"
-#include "hc_internal.h"
+#include "hc_host.h"
 
 using namespace hcx;
 
-namespace {
+namespace hcx {
 
+namespace {
 thread_local std::string g_err;
+}
 
 hc_status fail(hc_status code, const char *fmt, ...)
 {
@@ -34,42 +35,11 @@ hc_status fail(hc_status code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(call)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(e_ == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "%s: %s (%s:%d)", \
-                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                 \
-    } while (0)
+void clear_error() { clear_error(); }
 
-// A grow-only device buffer; `moves` counts reallocations (captured graphs and
-// other holders of its address must notice when it moves).
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-    unsigned long long moves = 0;
-    hipError_t ensure(size_t bytes)
-    {
-        if (bytes <= cap) return hipSuccess;
-        moves++;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-            p = nullptr;
-            cap = 0;
-        }
-        size_t want = std::max<size_t>(bytes, 256);
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) cap = want;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
+const char *last_error() { return g_err.c_str(); }
+
+namespace {
 
 template <typename T>
 hipError_t upload(T **dst, const T *src, size_t count)
@@ -82,46 +52,7 @@ hipError_t upload(T **dst, const T *src, size_t count)
 }
 
 }  // namespace
-
-struct hc_system {
-    int n = 0, n_terms = 0, n_params = 0, kind = 0, T = 0;
-    unsigned deg2 = 0;
-    int64_t bezout = 0;
-    std::vector<int> deg;
-    bool has_const = false, has_map = false;
-    // device copies of the tables
-    int *d_slot_ptr = nullptr, *d_slot_term = nullptr, *d_slot_mult = nullptr;
-    double *d_term_const = nullptr;
-    int *d_map_ptr = nullptr, *d_map_col = nullptr;
-    double *d_map_val = nullptr;
-};
-
-struct hc_ctx {
-    int device = 0;
-    hipStream_t own_stream = nullptr;  // used by the host-buffer entry point
-    std::vector<hc_system *> systems;
-    DevBuf state;   // SoA path state
-    DevBuf coef;    // per-instance kernel tables (FP64 then FP32)
-    DevBuf io;      // device copies of host inputs/outputs for hc_track
-    DevBuf counter; // suspended-path counter, then two stage counters (profiling)
-    DevBuf queue;   // batch: per-pass job descriptors, work items, queue heads
-    std::vector<TrackArgs> h_jobs;   // host copies kept alive across the async uploads
-    std::vector<QueueItem> h_items;
-    // workspace generation: bumped whenever a buffer moves (captured graphs hold pointers)
-    unsigned long long generation = 0;
-    // hipGraph of the last hc_track_device call with use_graph, and its arguments
-    bool graph_valid = false;
-    std::vector<unsigned char> graph_key;
-    hipGraphExec_t graph_exec = nullptr;
-    // autotuner choices: key -> (lanes_per_path, tracks_per_item)
-    std::vector<std::pair<std::vector<unsigned char>, std::pair<int, int>>> tune;
-    // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
-    bool profiling = false;
-    bool profiled_call = false;
-    hipEvent_t ev[6] = {};
-    int launches_fp32 = 0, launches_fp64 = 0;
-    bool had_fp32 = false;
-};
+}  // namespace hcx
 
 extern "C" {
 
@@ -151,11 +82,11 @@ void hc_default_opts(hc_opts *o)
     o->lanes_per_path = 0;
 }
 
-const char *hc_last_error(void) { return g_err.c_str(); }
+const char *hc_last_error(void) { return last_error(); }
 
 hc_status hc_create(int device, hc_ctx **out)
 {
-    g_err.clear();
+    clear_error();
     if (!out) return fail(HC_E_INVALID, "hc_create: out is NULL");
     int count = 0;
     HIP_TRY(hipGetDeviceCount(&count));
@@ -208,7 +139,7 @@ void hc_destroy(hc_ctx *c)
 
 hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
 {
-    g_err.clear();
+    clear_error();
     if (!c || !d || !out) return fail(HC_E_INVALID, "hc_load_system: NULL argument");
     if (d->n < 1) return fail(HC_E_INVALID, "hc_load_system: n = %d", d->n);
     if (d->n > HC_MAX_N) return fail(HC_E_UNSUPPORTED, "hc_load_system: n = %d > %d", d->n, HC_MAX_N);
@@ -237,6 +168,7 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
 
     hc_system *s = new (std::nothrow) hc_system;
     if (!s) return fail(HC_E_OOM, "hc_load_system: out of host memory");
+    s->device = c->device;
     s->n = n;
     s->n_terms = nt;
     s->n_params = d->n_params;
@@ -327,7 +259,7 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
 
 hc_status hc_free_system(hc_ctx *c, hc_system *s)
 {
-    g_err.clear();
+    clear_error();
     if (!c || !s) return fail(HC_E_INVALID, "hc_free_system: NULL argument");
     auto it = std::find(c->systems.begin(), c->systems.end(), s);
     if (it == c->systems.end()) return fail(HC_E_INVALID, "hc_free_system: system not owned by this context");
@@ -342,7 +274,7 @@ hc_status hc_free_system(hc_ctx *c, hc_system *s)
 
 hc_status hc_system_dims(const hc_system *s, int32_t *n, int64_t *bezout)
 {
-    g_err.clear();
+    clear_error();
     if (!s) return fail(HC_E_INVALID, "hc_system_dims: NULL system");
     if (n) *n = s->n;
     if (bezout) *bezout = s->bezout;
@@ -351,7 +283,7 @@ hc_status hc_system_dims(const hc_system *s, int32_t *n, int64_t *bezout)
 
 hc_status hc_total_degree_start(const hc_system *s, int64_t first, int64_t count, hc_c64 *out)
 {
-    g_err.clear();
+    clear_error();
     if (!s || (count > 0 && !out)) return fail(HC_E_INVALID, "hc_total_degree_start: NULL argument");
     if (first < 0 || count < 0 || first + count > s->bezout)
         return fail(HC_E_INVALID, "hc_total_degree_start: range [%lld, %lld) outside [0, %lld)",
@@ -637,7 +569,7 @@ hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, in
                           const hc_c64 *gamma, const hc_opts *opts, hc_c64 *endpoints, int32_t *status,
                           hc_track_info *info, void *stream)
 {
-    g_err.clear();
+    clear_error();
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool graph = c && opts && opts->use_graph && st != nullptr && opts->steps_per_launch == 0 &&
                        !c->profiling;
@@ -699,7 +631,7 @@ hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_
                       const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma, const hc_opts *opts,
                       hc_c64 *endpoints, int32_t *status, hc_track_info *info, void *stream, hc_opts *best)
 {
-    g_err.clear();
+    clear_error();
     if (!c || !s || !best) return fail(HC_E_INVALID, "hc_autotune: NULL argument");
     hc_opts o;
     if (opts) o = *opts;
@@ -765,7 +697,7 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
                    const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma,
                    const hc_opts *opts, hc_c64 *endpoints, int32_t *status, hc_track_info *info)
 {
-    g_err.clear();
+    clear_error();
     if (!c || !s) return fail(HC_E_INVALID, "hc_track: NULL context or system");
     if (n_start < 0 || n_inst < 0) return fail(HC_E_INVALID, "hc_track: negative size");
     const long long total = (long long)n_start * n_inst;
@@ -821,7 +753,7 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
 hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts_in,
                                 void *stream)
 {
-    g_err.clear();
+    clear_error();
     if (!c || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(HC_E_INVALID, "hc_track_batch_device: bad arguments");
     hc_opts o;
     if (opts_in) o = *opts_in;
@@ -849,8 +781,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         const hc_job &j = jobs[k];
         if (!j.sys) return fail(HC_E_INVALID, "hc_track_batch_device: job %d has no system", k);
         const hc_system *s = j.sys;
-        if (std::find(c->systems.begin(), c->systems.end(), s) == c->systems.end())
-            return fail(HC_E_INVALID, "hc_track_batch_device: job %d's system is not loaded in this context", k);
+        if (s->device != c->device)
+            return fail(HC_E_INVALID, "hc_track_batch_device: job %d's system lives on another device", k);
         if (j.n_start < 0 || j.n_inst < 0) return fail(HC_E_INVALID, "hc_track_batch_device: job %d negative size", k);
         if (s->n < 2) return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: job %d has n = 1", k);
         Plan p{};
@@ -1041,7 +973,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
 
 hc_status hc_set_profiling(hc_ctx *c, int32_t enable)
 {
-    g_err.clear();
+    clear_error();
     if (!c) return fail(HC_E_INVALID, "hc_set_profiling: NULL context");
     c->profiling = enable != 0;
     return HC_OK;
@@ -1049,7 +981,7 @@ hc_status hc_set_profiling(hc_ctx *c, int32_t enable)
 
 hc_status hc_last_profile(hc_ctx *c, hc_profile *out)
 {
-    g_err.clear();
+    clear_error();
     if (!c || !out) return fail(HC_E_INVALID, "hc_last_profile: NULL argument");
     if (!c->profiled_call) return fail(HC_E_INVALID, "hc_last_profile: no profiled call on this context");
     HIP_TRY(hipSetDevice(c->device));
@@ -1075,7 +1007,7 @@ hc_status hc_last_profile(hc_ctx *c, hc_profile *out)
 hc_status hc_homogenize(int32_t n, int32_t n_entries, const int32_t *entry_ptr, const int32_t *scalar,
                         const int32_t *coef, const int32_t *exp, int32_t K, int32_t M, int32_t *out)
 {
-    g_err.clear();
+    clear_error();
     if (n < 1 || n_entries < 0 || K < 1 || M < 1)
         return fail(HC_E_INVALID, "hc_homogenize: bad sizes n=%d entries=%d K=%d M=%d", n, n_entries, K, M);
     if (n_entries > 0 && (!entry_ptr || !out)) return fail(HC_E_INVALID, "hc_homogenize: NULL argument");

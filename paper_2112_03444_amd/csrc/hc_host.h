@@ -1,0 +1,99 @@
+// hc_host.h -- host-side definitions shared by the C-ABI library's sources:
+// error reporting, grow-only device buffers, loaded systems and contexts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hc.h"
+#include "hc_internal.h"
+
+namespace hcx {
+
+// Records the message of the last error on this thread and returns `code`.
+hc_status fail(hc_status code, const char *fmt, ...);
+void clear_error();
+
+#define HIP_TRY(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return ::hcx::fail(e_ == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "%s: %s (%s:%d)", \
+                               #call, hipGetErrorString(e_), __FILE__, __LINE__);               \
+    } while (0)
+
+// A grow-only device buffer; `moves` counts reallocations (captured graphs and
+// other holders of its address must notice when it moves).
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    unsigned long long moves = 0;
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= cap) return hipSuccess;
+        moves++;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            cap = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+}  // namespace hcx
+
+struct hc_system {
+    int device = 0;
+    int n = 0, n_terms = 0, n_params = 0, kind = 0, T = 0;
+    unsigned deg2 = 0;
+    int64_t bezout = 0;
+    std::vector<int> deg;
+    bool has_const = false, has_map = false;
+    // device copies of the tables
+    int *d_slot_ptr = nullptr, *d_slot_term = nullptr, *d_slot_mult = nullptr;
+    double *d_term_const = nullptr;
+    int *d_map_ptr = nullptr, *d_map_col = nullptr;
+    double *d_map_val = nullptr;
+};
+
+struct hc_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;  // used by the host-buffer entry point
+    std::vector<hc_system *> systems;
+    hcx::DevBuf state;   // SoA path state
+    hcx::DevBuf coef;    // per-instance kernel tables (FP64 then FP32)
+    hcx::DevBuf io;      // device copies of host inputs/outputs for hc_track
+    hcx::DevBuf counter; // suspended-path counter, then two stage counters (profiling)
+    hcx::DevBuf queue;   // batch: per-pass job descriptors, work items, queue heads
+    std::vector<hcx::TrackArgs> h_jobs;   // host copies kept alive across the async uploads
+    std::vector<hcx::QueueItem> h_items;
+    // hipGraph of the last hc_track_device call with use_graph, and its arguments
+    bool graph_valid = false;
+    std::vector<unsigned char> graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    // autotuner choices: key -> (lanes_per_path, tracks_per_item)
+    std::vector<std::pair<std::vector<unsigned char>, std::pair<int, int>>> tune;
+    // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
+    bool profiling = false;
+    bool profiled_call = false;
+    hipEvent_t ev[6] = {};
+    int launches_fp32 = 0, launches_fp64 = 0;
+    bool had_fp32 = false;
+};

@@ -336,3 +336,122 @@ class Context:
         o = opts if opts is not None else default_opts()
         _check(lib().hc_track_batch_device(self.handle, len(jobs), arr, ctypes.byref(o),
                                            ctypes.c_void_p(stream.cuda_stream)))
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch_requests", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_int64), ("opts", Opts)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("sys", ctypes.c_void_p), ("n_start", ctypes.c_int32), ("n_inst", ctypes.c_int32),
+                ("start", ctypes.c_void_p), ("p_start", ctypes.c_void_p), ("p_target", ctypes.c_void_p),
+                ("gamma", ctypes.c_void_p), ("endpoints", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "batches", "tracks_completed",
+                                              "latencies", "peak_bytes")] + \
+               [(k, ctypes.c_double) for k in ("wall_s", "mean_ms", "p50_ms", "p99_ms", "max_ms")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_server_bound = False
+
+
+def _bind_server():
+    global _server_bound
+    if _server_bound:
+        return
+    L = lib()
+    P, I64 = ctypes.c_void_p, ctypes.c_int64
+    L.hc_server_default_opts.restype = None
+    L.hc_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+    L.hc_server_create.restype = ctypes.c_int
+    L.hc_server_create.argtypes = [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
+    L.hc_server_submit.restype = ctypes.c_int
+    L.hc_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(I64)]
+    L.hc_server_poll.restype = ctypes.c_int
+    L.hc_server_poll.argtypes = [P, I64, ctypes.POINTER(ctypes.c_int32)]
+    L.hc_server_wait.restype = ctypes.c_int
+    L.hc_server_wait.argtypes = [P, I64]
+    L.hc_server_get_stats.restype = ctypes.c_int
+    L.hc_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    L.hc_server_reset_stats.restype = ctypes.c_int
+    L.hc_server_reset_stats.argtypes = [P]
+    L.hc_server_destroy.restype = ctypes.c_int
+    L.hc_server_destroy.argtypes = [P]
+    _server_bound = True
+
+
+class Server:
+    """hc_server_*: continuous batching of host-buffer solve requests."""
+
+    def __init__(self, ctx: Context, max_inflight: int = 3, max_batch_requests: int = 64,
+                 hbm_budget: int = 8 << 30, opts: Optional[Opts] = None):
+        _bind_server()
+        so = ServerOpts()
+        lib().hc_server_default_opts(ctypes.byref(so))
+        so.max_inflight = max_inflight
+        so.max_batch_requests = max_batch_requests
+        so.hbm_budget = hbm_budget
+        if opts is not None:
+            so.opts = opts
+        h = ctypes.c_void_p()
+        _check(lib().hc_server_create(ctx.handle, ctypes.byref(so), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self._out = {}
+
+    def submit(self, s: System, p_target, gamma=None, start=None, p_start=None, n_start=None,
+               with_info: bool = False) -> int:
+        p = np.ascontiguousarray(p_target, np.complex128)
+        if p.ndim == 1:
+            p = p[None, :]
+        n_inst = p.shape[0]
+        g = None if gamma is None else np.ascontiguousarray(
+            np.broadcast_to(np.asarray(gamma, np.complex128), (n_inst,)))
+        st_pts = None if start is None else np.ascontiguousarray(start, np.complex128).reshape(-1, s.n)
+        if n_start is None:
+            n_start = s.bezout if st_pts is None else st_pts.shape[0]
+        ps = None if p_start is None else np.ascontiguousarray(p_start, np.complex128)
+        ep = np.zeros((n_inst, n_start, s.n), np.complex128)
+        status = np.zeros((n_inst, n_start), np.int32)
+        info = np.zeros((n_inst, n_start), INFO_DTYPE) if with_info else None
+        r = Request(s.handle, n_start, n_inst, _ptr(st_pts), _ptr(ps), _ptr(p), _ptr(g), _ptr(ep), _ptr(status),
+                    _ptr(info))
+        t = ctypes.c_int64()
+        _check(lib().hc_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._out[t.value] = (ep, status, info)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(lib().hc_server_poll(self.handle, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(lib().hc_server_wait(self.handle, ticket))
+        return self._out.pop(ticket)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().hc_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        _check(lib().hc_server_reset_stats(self.handle))
+
+    def close(self):
+        if self.handle:
+            _check(lib().hc_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
