@@ -112,7 +112,7 @@ typedef struct {
     double h_max;       /* largest step                                        (0.1)   */
     double beta_inc;    /* growth factor after n_inc consecutive accepts       (2)     */
     double beta_dec;    /* factor applied on a rejected step                   (0.5)   */
-    double tau64;       /* FP64 corrector: ||dx||_2 <= tau (1 + ||x||_2)      (1e-8)  */
+    double tau64;       /* FP64 corrector: ||dx||_2 <= tau (1 + ||x||_2)      (1e-6)  */
     double tau32;       /* FP32 corrector tolerance in mixed mode              (1e-4)  */
     double pred_tol;    /* first correction above pred_tol (1 + ||x||_2)
                            rejects the step (prediction too far off)          (1e-2)  */
@@ -133,7 +133,9 @@ typedef struct {
                                  hipGraph on the first call and replay it while the
                                  arguments stay the same (needs a non-null stream,
                                  steps_per_launch 0, profiling off)             (0)     */
-    int32_t reserved;
+    int32_t fp64_residual;    /* mixed mode: the FP32 pass's Newton corrector evaluates
+                                 H(x, t) in FP64 at an FP64 point and solves with the
+                                 FP32 LU (iterative refinement)                  (0)     */
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;

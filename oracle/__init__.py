@@ -39,7 +39,7 @@ class Opts(ctypes.Structure):
 
 # The paper prints no step-control constants (section 3 only says "a number of
 # small steps"); these are the values both sides are run with.
-DEFAULTS = dict(h0=0.05, h_min=1e-7, h_max=0.1, beta_inc=2.0, beta_dec=0.5, tau=1e-8,
+DEFAULTS = dict(h0=0.05, h_min=1e-7, h_max=0.1, beta_inc=2.0, beta_dec=0.5, tau=1e-6,
                 pred_tol=1e-2, tau_refine=1e-14, inf_bound=1e7, eta_max=1e-10, n_inc=5, max_newton=3,
                 max_steps=5000, max_refine=10)
 

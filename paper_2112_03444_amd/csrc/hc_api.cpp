@@ -65,7 +65,7 @@ void hc_default_opts(hc_opts *o)
     o->h_max = 0.1;
     o->beta_inc = 2.0;
     o->beta_dec = 0.5;
-    o->tau64 = 1e-8;
+    o->tau64 = 1e-6;
     o->tau32 = 1e-4;
     o->pred_tol = 1e-2;
     o->tau_refine = 1e-14;
@@ -80,6 +80,7 @@ void hc_default_opts(hc_opts *o)
     o->steps_per_launch = 0;
     o->tracks_per_item = 0;
     o->lanes_per_path = 0;
+    o->fp64_residual = 0;
 }
 
 const char *hc_last_error(void) { return last_error(); }
@@ -514,6 +515,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         ta.tau = fp32 ? o.tau32 : o.tau64;
         ta.t_final = t_final;
         ta.escalate = escalate;
+        ta.ir = fp32 && o.fp64_residual ? 1 : 0;
         ta.launch_steps = o.steps_per_launch;
         ta.stage_count = prof ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
         for (;;) {
@@ -895,6 +897,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             ta.t_final = fp32 ? 1.0 - o.t_end : 1.0;
             ta.launch_steps = 0;
             ta.escalate = fp32 ? 1 : 0;
+            ta.ir = fp32 && o.fp64_residual ? 1 : 0;
             ta.h0 = o.h0;
             ta.h_min = o.h_min;
             ta.h_max = o.h_max;

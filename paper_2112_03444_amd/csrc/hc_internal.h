@@ -70,6 +70,7 @@ struct TrackArgs {
     double t_final;           // 1, or 1 - t_end for the FP32 pass
     int launch_steps;         // steps per path in this launch, 0 = unlimited
     int escalate;             // FP32 pass: failures go back to RUNNING for FP64
+    int ir;                   // FP32 pass: FP64 right-hand side in Newton stages
     double h0, h_min, h_max, beta_inc, beta_dec, tau, pred_tol, inf2;
     int n_inc, max_newton, max_steps;
     TrackState s;

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                  "tau_refine", "inf_bound", "eta_max", "t_end")] + \
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
-                 "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "reserved")]
+                 "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual")]
 
 
 class Job(ctypes.Structure):

@@ -89,12 +89,13 @@ def test_dense_fp64_each_n(hc, ctx, n, lanes):
     ctx.free_system(sysh)
 
 
-@pytest.mark.parametrize("lanes", [0, 1])
+@pytest.mark.parametrize("lanes,ir", [(0, 0), (0, 1), (1, 0)])
 @pytest.mark.parametrize("n", [3, 6, 8])
-def test_mixed_mode_residual_and_sets(hc, ctx, n, lanes):
+def test_mixed_mode_residual_and_sets(hc, ctx, n, lanes, ir):
     S, coef, gam = hc_inputs.dense_quadratic_instances(n, 4, seed=2000 + n)
     sysh = ctx.load_system(S)
-    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed", lanes_per_path=lanes))
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed", lanes_per_path=lanes,
+                                                                   fp64_residual=ir))
     oep, ost, _ = oracle.track(S, coef, gam)
     ok = st == hc.HC_T_SUCCESS
     assert np.all(info["residual"][ok] <= 1e-10)
@@ -123,10 +124,11 @@ def test_config2_full_batch_fp64_sampled(hc, ctx):
         check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
 
 
-def test_config2_full_batch_mixed_sampled(hc, ctx):
+@pytest.mark.parametrize("ir", [0, 1])
+def test_config2_full_batch_mixed_sampled(hc, ctx, ir):
     S, coef, gam = hc_inputs.workload("dense8_batch512")
     sysh = ctx.load_system(S)
-    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed"))
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed", fp64_residual=ir))
     ok = st == hc.HC_T_SUCCESS
     assert ok.mean() >= 0.999, np.bincount(st.ravel(), minlength=7)
     assert np.all(info["residual"][ok] <= 1e-10)
@@ -262,7 +264,7 @@ def test_bad_layout_option(hc, ctx):
         ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=3))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_ir"])
 @pytest.mark.parametrize("n", [3, 5, 8])
 def test_parameter_homotopy(hc, ctx, n, precision):
     """Coefficients interpolated from a solved start instance to two targets
@@ -274,8 +276,9 @@ def test_parameter_homotopy(hc, ctx, n, precision):
     assert (st0 == hc.HC_T_SUCCESS).all()
     starts = ep0[0]
     ps = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    ir = precision == "mixed_ir"
     ep, st, info = ctx.track(ps, coef[1:], start=starts, p_start=coef[0],
-                             opts=hc.default_opts(precision=precision))
+                             opts=hc.default_opts(precision="mixed" if ir else precision, fp64_residual=int(ir)))
     oep, ost, _ = oracle.track(S, coef[1:], start=starts, coef0=coef[0], kind=oracle.LINEAR)
     tep, tst, _ = ctx.track(td, coef[1:], gam[1:])
     for i in range(2):
