@@ -1,0 +1,125 @@
+"""Start solutions of a generic parameter instance by monodromy.
+
+TEST INFRASTRUCTURE ONLY (like the rest of ``oracle/``): it writes the start
+instance and start solutions that the parameter-homotopy workloads track from.
+Those are inputs, consumed alike by the oracle and by the HIP path.
+
+The paper solves its vision problems from a random complex start instance whose
+solutions were computed offline by monodromy (section 7).  This restates the
+published method (Duff, Hill, Jensen, Lee, Leykin, Sommars, IMA J. Numer. Anal.
+2019), with the oracle's FP64 tracker doing every path:
+
+1. fabricate one exact pair: random complex x0 and coefficients c0, then one
+   coefficient per equation is solved for so that F(x0; c0) = 0;
+2. loop c0 -> ca -> cb -> c0 over fresh random complex instances ca, cb (linear
+   coefficient segments: the paper's parameter homotopy), carrying every known
+   solution around the loop; new distinct endpoints join the set;
+3. stop once the set has not grown for `stall` consecutive loops.
+
+Usage (writes tests/golden/start_triang4.npz and prints its sha256):
+
+    python -m oracle.monodromy triang4
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import LINEAR, SUCCESS, eval_system, residual, track
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _cn(rng, shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+def monomials(system, x):
+    """Value of every term's monomial at x."""
+    return np.prod(np.asarray(x)[None, :] ** system.term_exp, axis=1)
+
+
+def fabricate_pair(system, rng):
+    """(c0, x0) with F(x0; c0) = 0 exactly up to rounding: per equation, the
+    coefficient of its term with the largest monomial value is solved for."""
+    x0 = _cn(rng, system.n)
+    c0 = _cn(rng, system.n_terms)
+    m = monomials(system, x0)
+    for i in range(system.n):
+        ks = np.flatnonzero(system.term_eq == i)
+        k = ks[np.argmax(np.abs(m[ks]))]
+        rest = np.sum(c0[ks] * m[ks]) - c0[k] * m[k]
+        c0[k] = -rest / m[k]
+    return c0, x0
+
+
+def distinct_rows(sols, tol=1e-8):
+    """Rows of `sols` with duplicates (relative inf-norm distance <= tol) removed;
+    the first of equal rows is kept."""
+    sols = np.asarray(sols)
+    keep = []
+    for k in range(len(sols)):
+        if keep:
+            y = sols[keep]
+            d = np.max(np.abs(y - sols[k]), axis=1) / np.maximum(1.0, np.max(np.abs(y), axis=1))
+            if np.min(d) <= tol:
+                continue
+        keep.append(k)
+    return sols[keep]
+
+
+def _segment(system, c_from, c_to, sols, n_threads):
+    ep, st, _ = track(system, c_to[None, :], start=sols, coef0=c_from, kind=LINEAR, n_threads=n_threads)
+    return ep[0][st[0] == SUCCESS]
+
+
+def monodromy(system, seed=0, stall=10, max_loops=500, n_threads=None, log=print):
+    """(c0, solutions [N, n]) of a generic instance of the linear-coefficient
+    family with the support of `system`."""
+    rng = np.random.default_rng(seed)
+    c0, x0 = fabricate_pair(system, rng)
+    sols = x0[None, :]
+    quiet = 0
+    t0 = time.time()
+    for loop in range(max_loops):
+        ca, cb = _cn(rng, system.n_terms), _cn(rng, system.n_terms)
+        xa = _segment(system, c0, ca, sols, n_threads)
+        xb = _segment(system, ca, cb, xa, n_threads)
+        back = _segment(system, cb, c0, xb, n_threads)
+        merged = distinct_rows(np.concatenate([sols, back])) if len(back) else sols
+        grew = len(merged) - len(sols)
+        sols = merged
+        quiet = 0 if grew > 0 else quiet + 1
+        log(f"loop {loop}: {len(sols)} solutions (+{grew}), {time.time() - t0:.0f} s")
+        if quiet >= stall:
+            break
+    return c0, sols
+
+
+def check(system, c0, sols):
+    """Every solution has a tiny residual and the set is pairwise distinct."""
+    eta = max(residual(system, c0, x) for x in sols)
+    d = len(distinct_rows(sols)) == len(sols)
+    return eta, d
+
+
+def main(argv):
+    name = argv[1] if len(argv) > 1 else "triang4"
+    if name != "triang4":
+        raise SystemExit(f"unknown family {name}")
+    import hc_inputs.vision as V
+    S = V.triangulation_system()
+    c0, sols = monodromy(S, seed=4)
+    eta, d = check(S, c0, sols)
+    print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
+    out = os.path.join(ROOT, "tests", "golden", "start_triang4.npz")
+    np.savez(out, coef0=c0, solutions=sols)
+    print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
+
+
+if __name__ == "__main__":
+    main(sys.argv)
