@@ -68,10 +68,13 @@ def time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch):
 
 
 def roofline(profs, n, kind):
+    """Tracker launches of one mode.  The mixed-precision tracker is one launch of
+    k_track_grp<.., float, ..> whose escalated paths run their FP64 stages inside
+    the same launch, so both stage counts go to that launch."""
     key = "fp32" if kind == "fp32" else "fp64"
     ms = float(np.mean([p[f"ms_track_{key}"] for p in profs]))
     launches = float(np.mean([p[f"launches_{key}"] for p in profs]))
-    stages = float(np.mean([p[f"stages_{key}"] for p in profs]))
+    stages = float(np.mean([p[f"stages_{key}"] + (p["stages_fp64"] if key == "fp32" else 0.0) for p in profs]))
     flops = stages * w_stage(n)
     per_launch_ms = ms / max(launches, 1.0)
     achieved = flops / launches / (per_launch_ms * 1e-3) / 1e12

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define HC_MAX_N 8 /* largest number of unknowns the GPU path handles */
+#define HC_MAX_N 16 /* largest number of unknowns the GPU path handles */
 
 typedef struct {
     double re, im;
@@ -162,6 +162,22 @@ void hc_destroy(hc_ctx *ctx);
  * Errors: HC_E_INVALID (malformed description), HC_E_UNSUPPORTED (n > HC_MAX_N,
  * a term of degree > 2, an equation of degree 0), HC_E_OOM, HC_E_DEVICE. */
 hc_status hc_load_system(hc_ctx *ctx, const hc_system_desc *desc, hc_system **out);
+
+/* Evaluation-table layout of a loaded system. */
+typedef enum {
+    HC_LAYOUT_AUTO = 0,   /* dense tables for n <= 8, term lists above             */
+    HC_LAYOUT_DENSE = 1,  /* every monomial of degree <= 2 gets a table slot
+                             (c, L, Q per equation); n <= 8                       */
+    HC_LAYOUT_TERMS = 2   /* per equation the list of its own terms (section 6's
+                             term tables), each c x_a x_b; n <= 16              */
+} hc_layout;
+
+/* hc_load_system with an explicit table layout (hc_load_system uses
+ * HC_LAYOUT_AUTO).  Both layouts compute the same homotopy; the term lists do
+ * work in proportion to the terms a system has, the dense tables to n^3.
+ * Errors: as hc_load_system, and HC_E_UNSUPPORTED for HC_LAYOUT_DENSE with n > 8
+ * or an unknown layout. */
+hc_status hc_load_system_layout(hc_ctx *ctx, const hc_system_desc *desc, int32_t layout, hc_system **out);
 
 /* Releases a loaded system. */
 hc_status hc_free_system(hc_ctx *ctx, hc_system *sys);
@@ -323,14 +339,17 @@ hc_status hc_server_destroy(hc_server *srv);
 typedef struct {
     float ms_prep;          /* kernel-table preparation                     */
     float ms_init;          /* path-state initialisation                    */
-    float ms_track_fp32;    /* all FP32 tracking launches (mixed mode)      */
-    float ms_track_fp64;    /* all FP64 tracking launches                   */
+    float ms_track_fp32;    /* mixed-mode tracking launches                 */
+    float ms_track_fp64;    /* FP64 tracking launches                       */
     float ms_refine;        /* endpoint refinement and classification       */
     int32_t launches_fp32;
     int32_t launches_fp64;
-    int32_t reserved;
-    int64_t stages_fp32;    /* stages executed by the FP32 launches         */
-    int64_t stages_fp64;    /* stages executed by the FP64 launches         */
+    float ms_crossing;      /* mixed mode: crossing check, FP64 re-tracking of
+                               crossed paths and their refinement           */
+    int64_t stages_fp32;    /* stages run in FP32                           */
+    int64_t stages_fp64;    /* stages run in FP64 (with the default lanes_per_path,
+                               mixed mode runs the FP64 stages of its escalated
+                               paths inside its own launches)                 */
 } hc_profile;
 
 /* Switches event timing and stage counting on (enable != 0) or off for the

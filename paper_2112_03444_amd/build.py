@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhc.so")
 SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp"),
-           os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip")]
+           os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip"),
+           os.path.join(CSRC, "hc_track_terms.hip")]
 ARCH = "gfx950"
 
 
@@ -29,20 +30,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def compile_cmd(out: str):
-    return [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-fPIC", "-shared", "-pthread", "-I", INCLUDE, "-I", CSRC, *SOURCES, "-o", out]
+FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-fPIC"]
 
 
 def build(verbose: bool = False) -> str:
-    """Always compiles (the caller asked for a build); returns the library path."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = compile_cmd(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    """Always compiles (the caller asked for a build); returns the library path.
+    The sources compile to objects in parallel, then link into libhc.so."""
+    import concurrent.futures
+    import tempfile
+
+    with tempfile.TemporaryDirectory(prefix="hc_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[hipcc(), *FLAGS, "-pthread", "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        workers = max(1, min(len(cmds), os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            for f in [ex.submit(subprocess.check_call, c) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp%d" % os.getpid()
+        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
+        os.replace(tmp, LIB)
     return LIB
 
 

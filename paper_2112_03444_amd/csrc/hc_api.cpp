@@ -115,6 +115,7 @@ static void free_system_tables(hc_system *s)
     (void)hipFree(s->d_map_ptr);
     (void)hipFree(s->d_map_col);
     (void)hipFree(s->d_map_val);
+    (void)hipFree(s->d_vars);
 }
 
 void hc_destroy(hc_ctx *c)
@@ -140,10 +141,22 @@ void hc_destroy(hc_ctx *c)
 
 hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
 {
+    return hc_load_system_layout(c, d, HC_LAYOUT_AUTO, out);
+}
+
+hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layout, hc_system **out)
+{
     clear_error();
     if (!c || !d || !out) return fail(HC_E_INVALID, "hc_load_system: NULL argument");
     if (d->n < 1) return fail(HC_E_INVALID, "hc_load_system: n = %d", d->n);
     if (d->n > HC_MAX_N) return fail(HC_E_UNSUPPORTED, "hc_load_system: n = %d > %d", d->n, HC_MAX_N);
+    if (layout == HC_LAYOUT_AUTO) layout = d->n <= 8 ? HC_LAYOUT_DENSE : HC_LAYOUT_TERMS;
+    if (layout != HC_LAYOUT_DENSE && layout != HC_LAYOUT_TERMS)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: layout %d", layout);
+    if (layout == HC_LAYOUT_DENSE && d->n > 8)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: dense tables need n <= 8 (n = %d)", d->n);
+    if (layout == HC_LAYOUT_TERMS && d->n < 2)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: term lists need n >= 2");
     if (d->n_terms < 1 || !d->term_eq || !d->term_exp)
         return fail(HC_E_INVALID, "hc_load_system: empty or missing term tables");
     if (d->kind != HC_TOTAL_DEGREE && d->kind != HC_PARAMETER)
@@ -174,18 +187,25 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
     s->n_terms = nt;
     s->n_params = d->n_params;
     s->kind = d->kind;
-    s->T = dense_terms(n);
+    s->layout = layout;
     s->deg.assign(n, 0);
+    for (int k = 0; k < nt; k++) {
+        if (d->term_eq[k] < 0 || d->term_eq[k] >= n) {
+            delete s;
+            return fail(HC_E_INVALID, "hc_load_system: term_eq[%d] = %d out of range", k, d->term_eq[k]);
+        }
+    }
+    // term lists: slot j of equation i is the j-th term of equation i
+    std::vector<int> eq_count(n, 0), term_pos(nt);
+    for (int k = 0; k < nt; k++) term_pos[k] = eq_count[d->term_eq[k]]++;
+    s->T = layout == HC_LAYOUT_DENSE ? dense_terms(n) : *std::max_element(eq_count.begin(), eq_count.end());
 
-    // a0: map every term to its slot in the dense kernel tables
+    // a0: map every term to its slot in the kernel tables
     const int n_slots = n * s->T;
     std::vector<std::vector<std::pair<int, int>>> slot_terms(n_slots);
+    std::vector<unsigned short> vars(layout == HC_LAYOUT_TERMS ? n_slots : 0, 0xFFFFu);
     for (int k = 0; k < nt; k++) {
         const int i = d->term_eq[k];
-        if (i < 0 || i >= n) {
-            delete s;
-            return fail(HC_E_INVALID, "hc_load_system: term_eq[%d] = %d out of range", k, i);
-        }
         int deg = 0, a = -1, b = -1;
         for (int j = 0; j < n; j++) {
             const int e = d->term_exp[(size_t)k * n + j];
@@ -204,6 +224,14 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
             return fail(HC_E_UNSUPPORTED, "hc_load_system: term %d has degree %d > 2", k, deg);
         }
         s->deg[i] = std::max(s->deg[i], deg);
+        if (layout == HC_LAYOUT_TERMS) {
+            // c x_a x_b with 0xFF for a missing factor (x_a^2: a = b)
+            if (deg == 2 && b < 0) b = a;
+            const int q = i * s->T + term_pos[k];
+            vars[q] = (unsigned short)((a < 0 ? 0xFFu : (unsigned)a) | ((b < 0 ? 0xFFu : (unsigned)b) << 8));
+            slot_terms[q].push_back({k, 1});
+            continue;
+        }
         int slot, mult = 1;
         if (deg == 0) slot = 0;
         else if (deg == 1) slot = 1 + a;
@@ -238,6 +266,7 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
     if (e == hipSuccess) e = upload(&s->d_slot_ptr, slot_ptr.data(), slot_ptr.size());
     if (e == hipSuccess) e = upload(&s->d_slot_term, slot_term.data(), slot_term.size());
     if (e == hipSuccess) e = upload(&s->d_slot_mult, slot_mult.data(), slot_mult.size());
+    if (e == hipSuccess && !vars.empty()) e = upload(&s->d_vars, vars.data(), vars.size());
     if (e == hipSuccess && d->coef_const) {
         s->has_const = true;
         e = upload(&s->d_term_const, reinterpret_cast<const double *>(d->coef_const), (size_t)nt * 2);
@@ -318,32 +347,38 @@ static hc_status check_opts(const hc_opts &o)
         !(o.beta_inc >= 1) || o.n_inc < 1 || o.max_newton < 0 || o.max_steps < 0 || o.max_refine < 0 ||
         o.steps_per_launch < 0 || o.tracks_per_item < 0)
         return fail(HC_E_INVALID, "opts: step-control values out of range");
-    if (o.lanes_per_path != 0 && o.lanes_per_path != 1 && o.lanes_per_path != 4 && o.lanes_per_path != 8)
-        return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4 or 8)", o.lanes_per_path);
+    if (o.lanes_per_path != 0 && o.lanes_per_path != 1 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
+        o.lanes_per_path != 16)
+        return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4, 8 or 16)", o.lanes_per_path);
     if (o.precision == HC_MIXED && !(o.t_end >= 0 && o.t_end < 1))
         return fail(HC_E_INVALID, "opts.t_end = %g must lie in [0, 1) in mixed mode", o.t_end);
     return HC_OK;
 }
 
-// Lanes per path: one row of [H_x | rhs] per lane (G = 4 for n <= 4, 8 for
-// n <= 8) unless one path per lane is asked for or n = 1.
-static int choose_lanes_per_path(const hc_opts &o, int n)
+// Lanes per path: one row of [H_x | rhs] per lane (dense tables: G = 4 for
+// n <= 4, 8 for n <= 8; term lists: always 16) unless one path per lane is asked
+// for (dense tables) or n = 1.  -1: the option does not fit the system.
+static int choose_lanes_per_path(const hc_opts &o, const hc_system *s)
 {
-    if (n < 2) return 1;
+    if (s->layout == HC_LAYOUT_TERMS) return (o.lanes_per_path == 0 || o.lanes_per_path == 16) ? 16 : -1;
+    if (s->n < 2) return 1;
     if (o.lanes_per_path == 1) return 1;
-    const int g = group_lanes(n);
-    if (o.lanes_per_path != 0 && o.lanes_per_path < g) return -1;  // too few lanes for n rows
+    const int g = group_lanes(s->n);
+    if (o.lanes_per_path != 0 && o.lanes_per_path != g && o.lanes_per_path < g) return -1;  // too few lanes
+    if (o.lanes_per_path == 16) return -1;
     return g;
 }
 
-// Paths per wavefront work item.  The paths of an item go through the item's
-// lanes (or lane groups) by refill, so more paths per item balance better but
-// leave fewer items to spread over the 1024 SIMDs: aim at 8 paths per group.
+static int lanes_for(const hc_system *s) { return s->layout == HC_LAYOUT_TERMS ? 16 : group_lanes(s->n); }
+
+// Paths per work item.  Group layouts pop items from a device counter, so small
+// items balance the wavefronts (measured best: 2 paths per lane group); the
+// one-path-per-lane layout has fixed items of 64 paths.
 static int choose_tracks_per_item(const hc_opts &o, int n_start, int lanes)
 {
     if (o.tracks_per_item > 0) return o.tracks_per_item;
     const int slots = 64 / lanes;
-    return std::min(n_start, lanes == 1 ? 64 : 8 * slots);
+    return std::max(1, std::min(n_start, lanes == 1 ? 64 : 2 * slots));
 }
 
 template <typename T>
@@ -476,11 +511,14 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ia.start = reinterpret_cast<const double *>(start);
     ia.h0 = o.h0;
     ia.s = S;
+    ia.retrack = 0;
     HIP_TRY(launch_init(ia, st));
     if (prof) HIP_TRY(hipEventRecord(c->ev[2], st));
 
-    const int lanes = choose_lanes_per_path(o, n);
-    if (lanes < 0) return fail(HC_E_INVALID, "opts.lanes_per_path = %d is below n = %d", o.lanes_per_path, n);
+    const int lanes = choose_lanes_per_path(o, s);
+    if (lanes < 0)
+        return fail(HC_E_INVALID, "opts.lanes_per_path = %d does not fit this system (n = %d, %s tables)",
+                    o.lanes_per_path, n, s->layout == HC_LAYOUT_TERMS ? "term-list" : "dense");
     if (param && lanes == 1)
         return fail(HC_E_UNSUPPORTED, "hc_track: parameter homotopies need lanes_per_path 0, 4 or 8 and n >= 2");
     const int tpi = choose_tracks_per_item(o, n_start, lanes);
@@ -506,22 +544,34 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ta.max_steps = o.max_steps;
     ta.s = S;
     ta.n_suspended = static_cast<unsigned *>(c->counter.p);
+    ta.head = reinterpret_cast<unsigned *>(static_cast<char *>(c->counter.p) + 32);
+    ta.vars = s->d_vars;
+    ta.n_tslots = s->T;
     const int wpb = 4;
 
     // one pass = launches until no path is left suspended by steps_per_launch
     auto run_pass = [&](bool fp32, double t_final, int escalate) -> hc_status {
         ta.coef = fp32 ? (const void *)tab32 : (const void *)tab64;
         ta.coef0 = !param ? nullptr : fp32 ? (const void *)tab32_start : (const void *)tab64_start;
+        ta.coef64 = tab64;
+        ta.coef0_64 = tab64_start;
         ta.tau = fp32 ? o.tau32 : o.tau64;
+        ta.tau64 = o.tau64;
         ta.t_final = t_final;
+        ta.t_switch = fp32 ? std::min(1.0 - o.t_end, t_final) : t_final;
         ta.escalate = escalate;
         ta.ir = fp32 && o.fp64_residual ? 1 : 0;
         ta.launch_steps = o.steps_per_launch;
-        ta.stage_count = prof ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
+        ta.stage_count = !prof ? nullptr : lanes == 1 ? stage_ctr + (fp32 ? 0 : 1) : stage_ctr;
         for (;;) {
             if (o.steps_per_launch > 0) HIP_TRY(hipMemsetAsync(ta.n_suspended, 0, sizeof(unsigned), st));
-            if (lanes == 1) HIP_TRY(launch_track(n, fp32, ta, wpb, st));
-            else HIP_TRY(launch_track_group(n, fp32, ta, wpb, st));
+            if (lanes == 1) {
+                HIP_TRY(launch_track(n, fp32, ta, wpb, st));
+            } else {
+                HIP_TRY(launch_fill_u32(ta.head, 0u, 1, st));
+                if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_track_terms(fp32, ta, st));
+                else HIP_TRY(launch_track_group(n, fp32, ta, st));
+            }
             if (fp32) c->launches_fp32++;
             else c->launches_fp64++;
             if (o.steps_per_launch == 0) break;
@@ -532,14 +582,25 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         }
         return HC_OK;
     };
-    if (mixed) {
-        rc = run_pass(true, 1.0 - o.t_end, 1);
+    if (lanes > 1 && mixed) {
+        // group tracker: one launch; failed paths and the end zone go on in FP64
+        // inside the kernel
+        rc = run_pass(true, 1.0, 0);
         if (rc != HC_OK) return rc;
         c->had_fp32 = true;
+        if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
+    } else {
+        // lane tracker: an FP32 pass to 1 - t_end that hands its failures back,
+        // then the FP64 pass
+        if (mixed) {
+            rc = run_pass(true, 1.0 - o.t_end, 1);
+            if (rc != HC_OK) return rc;
+            c->had_fp32 = true;
+        }
+        if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
+        rc = run_pass(false, 1.0, 0);
+        if (rc != HC_OK) return rc;
     }
-    if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
-    rc = run_pass(false, 1.0, 0);
-    if (rc != HC_OK) return rc;
     if (prof) HIP_TRY(hipEventRecord(c->ev[4], st));
 
     RefineArgs ra;
@@ -556,9 +617,34 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ra.endpoints = reinterpret_cast<double *>(endpoints);
     ra.status = status;
     ra.info = info;
-    HIP_TRY(launch_refine(n, ra, st));
+    ra.n = n;
+    ra.n_tslots = s->T;
+    ra.vars = s->d_vars;
+    if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
+    else HIP_TRY(launch_refine(n, ra, st));
+    if (prof) HIP_TRY(hipEventRecord(c->ev[5], st));
+    if (mixed) {
+        // crossing check: paths that ended on the same root start over in FP64
+        DedupArgs da;
+        da.n = n;
+        da.n_start = n_start;
+        da.n_inst = n_inst;
+        da.total = total;
+        da.tol = kCrossTol;
+        da.endpoints = reinterpret_cast<const double *>(endpoints);
+        da.status = status;
+        da.s = S;
+        HIP_TRY(launch_dedup(da, st));
+        InitArgs ir = ia;
+        ir.retrack = 1;
+        HIP_TRY(launch_init(ir, st));
+        rc = run_pass(false, 1.0, 0);
+        if (rc != HC_OK) return rc;
+        if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
+        else HIP_TRY(launch_refine(n, ra, st));
+    }
     if (prof) {
-        HIP_TRY(hipEventRecord(c->ev[5], st));
+        HIP_TRY(hipEventRecord(c->ev[6], st));
         c->profiled_call = true;
     }
     return HC_OK;
@@ -645,10 +731,10 @@ hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_
     // candidates: lanes per path x paths per lane group (or per lane)
     std::vector<std::pair<int, int>> cand;
     if (s->n >= 2) {
-        const int g = group_lanes(s->n);
+        const int g = lanes_for(s);
         for (int per_group : {2, 4, 8, 16}) cand.push_back({g, per_group * (64 / g)});
     }
-    if (s->kind == HC_TOTAL_DEGREE)
+    if (s->kind == HC_TOTAL_DEGREE && s->layout == HC_LAYOUT_DENSE)
         for (int tpi : {64, 128, 256}) cand.push_back({1, tpi});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
@@ -775,6 +861,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         int n, T, n_slots, n_tab, tpi;
         bool param;
         size_t st_off, tab64_off, tab32_off;
+            InitArgs init;
     };
     std::vector<Plan> plan;
     size_t st_bytes = 0, tab_bytes = 0;
@@ -804,7 +891,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
                 return fail(HC_E_INVALID, "hc_track_batch_device: job %d has a NULL buffer", k);
         }
         p.n_tab = j.n_inst + (p.param ? 1 : 0);
-        p.tpi = choose_tracks_per_item(o, j.n_start, group_lanes(p.n));
+        p.tpi = choose_tracks_per_item(o, j.n_start, lanes_for(s));
         p.st_off = st_bytes;
         st_bytes += al((size_t)p.total * ((2 * p.n + 2) * 8 + 6 * 4));
         p.tab64_off = tab_bytes;
@@ -821,7 +908,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
 
     // job descriptors (one set per pass) and the two queues (total degree, parameter)
     c->h_jobs.assign((size_t)2 * n_jobs, TrackArgs{});
-    std::vector<QueueItem> q_td, q_par;
+    // queues: [dense | term lists] x [total degree | parameter]
+    std::vector<QueueItem> qs[4];
     std::vector<int> job_n(n_jobs);
     for (int k = 0; k < n_jobs; k++) {
         Plan &p = plan[k];
@@ -879,7 +967,9 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ia.start = reinterpret_cast<const double *>(p.j->start);
         ia.h0 = o.h0;
         ia.s = S;
+        ia.retrack = 0;
         HIP_TRY(launch_init(ia, st));
+        p.init = ia;
 
         for (int pass = 0; pass < 2; pass++) {
             const bool fp32 = pass == 0;
@@ -894,9 +984,14 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             ta.items_per_inst = (p.j->n_start + p.tpi - 1) / p.tpi;
             ta.n_items = ta.items_per_inst * p.j->n_inst;
             ta.total = p.total;
-            ta.t_final = fp32 ? 1.0 - o.t_end : 1.0;
+            // one launch in mixed mode: the FP32 tracker goes on in FP64 in-kernel
+            ta.coef64 = t64;
+            ta.coef0_64 = t64s;
+            ta.t_final = 1.0;
+            ta.t_switch = fp32 ? 1.0 - o.t_end : 1.0;
+            ta.tau64 = o.tau64;
             ta.launch_steps = 0;
-            ta.escalate = fp32 ? 1 : 0;
+            ta.escalate = 0;
             ta.ir = fp32 && o.fp64_residual ? 1 : 0;
             ta.h0 = o.h0;
             ta.h_min = o.h_min;
@@ -911,19 +1006,24 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             ta.max_steps = o.max_steps;
             ta.s = S;
             ta.n_suspended = static_cast<unsigned *>(c->counter.p);
-            ta.stage_count = c->profiling ? stage_ctr + (fp32 ? 0 : 1) : nullptr;
+            ta.stage_count = c->profiling ? stage_ctr : nullptr;
+            ta.vars = p.s->d_vars;
+            ta.n_tslots = p.s->T;
         }
-        std::vector<QueueItem> &q = p.param ? q_par : q_td;
+        std::vector<QueueItem> &q = qs[(p.s->layout == HC_LAYOUT_TERMS ? 2 : 0) + (p.param ? 1 : 0)];
         for (int i = 0; i < p.j->n_inst; i++)
             for (int tb = 0; tb < p.j->n_start; tb += p.tpi)
                 q.push_back({k, i, tb, std::min(tb + p.tpi, p.j->n_start)});
     }
     // larger systems first: their items are the longest
     auto by_n = [&](const QueueItem &x, const QueueItem &y) { return job_n[x.job] > job_n[y.job]; };
-    std::stable_sort(q_td.begin(), q_td.end(), by_n);
-    std::stable_sort(q_par.begin(), q_par.end(), by_n);
-    c->h_items = q_td;
-    c->h_items.insert(c->h_items.end(), q_par.begin(), q_par.end());
+    c->h_items.clear();
+    int q_off[5] = {0, 0, 0, 0, 0};
+    for (int qi = 0; qi < 4; qi++) {
+        std::stable_sort(qs[qi].begin(), qs[qi].end(), by_n);
+        c->h_items.insert(c->h_items.end(), qs[qi].begin(), qs[qi].end());
+        q_off[qi + 1] = (int)c->h_items.size();
+    }
     const size_t b_jobs = al(c->h_jobs.size() * sizeof(TrackArgs));
     const size_t b_items = al(std::max<size_t>(c->h_items.size(), 1) * sizeof(QueueItem));
     HIP_TRY(c->queue.ensure(b_jobs + b_items + 256));
@@ -936,24 +1036,27 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     if (!c->h_items.empty())
         HIP_TRY(hipMemcpyAsync(d_items, c->h_items.data(), c->h_items.size() * sizeof(QueueItem),
                                hipMemcpyHostToDevice, st));
-    const int n_td = (int)q_td.size(), n_par = (int)q_par.size();
     auto run_pass = [&](bool fp32) -> hc_status {
         const TrackArgs *pj = d_jobs + (fp32 ? 0 : n_jobs);
-        HIP_TRY(launch_fill_u32(heads, 0u, 2, st));
-        if (n_td) HIP_TRY(launch_track_queue(fp32, false, pj, d_items, n_td, heads, queue_waves(fp32, false), st));
-        if (n_par)
-            HIP_TRY(launch_track_queue(fp32, true, pj, d_items + n_td, n_par, heads + 1, queue_waves(fp32, true), st));
+        HIP_TRY(launch_fill_u32(heads, 0u, 4, st));
+        for (int qi = 0; qi < 4; qi++) {
+            const int cnt = q_off[qi + 1] - q_off[qi];
+            if (cnt == 0) continue;
+            const bool param = (qi & 1) != 0;
+            if (qi < 2)
+                HIP_TRY(launch_track_queue(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
+                                           queue_waves(fp32, param), st));
+            else
+                HIP_TRY(launch_track_queue_terms(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
+                                                 queue_waves_terms(fp32, param), st));
+        }
         return HC_OK;
     };
-    if (mixed) {
-        rc = run_pass(true);
-        if (rc != HC_OK) return rc;
-    }
-    rc = run_pass(false);
+    rc = run_pass(mixed);
     if (rc != HC_OK) return rc;
-    for (int k = 0; k < n_jobs; k++) {
+    auto refine_job = [&](int k) -> hc_status {
         const Plan &p = plan[k];
-        if (p.total == 0) continue;
+        if (p.total == 0) return HC_OK;
         const TrackArgs &ta = c->h_jobs[(size_t)n_jobs + k];
         RefineArgs ra;
         ra.coef = static_cast<const double *>(ta.coef);
@@ -969,7 +1072,43 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ra.endpoints = reinterpret_cast<double *>(p.j->endpoints);
         ra.status = p.j->status;
         ra.info = p.j->info;
-        HIP_TRY(launch_refine(p.n, ra, st));
+        ra.n = p.n;
+        ra.n_tslots = p.s->T;
+        ra.vars = p.s->d_vars;
+        if (p.s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
+        else HIP_TRY(launch_refine(p.n, ra, st));
+        return HC_OK;
+    };
+    for (int k = 0; k < n_jobs; k++) {
+        rc = refine_job(k);
+        if (rc != HC_OK) return rc;
+    }
+    if (mixed) {
+        // crossing check per job, then one FP64 pass over the queues and the
+        // refinement of the re-tracked paths
+        for (int k = 0; k < n_jobs; k++) {
+            const Plan &p = plan[k];
+            if (p.total == 0) continue;
+            DedupArgs da;
+            da.n = p.n;
+            da.n_start = p.j->n_start;
+            da.n_inst = p.j->n_inst;
+            da.total = p.total;
+            da.tol = kCrossTol;
+            da.endpoints = reinterpret_cast<const double *>(p.j->endpoints);
+            da.status = p.j->status;
+            da.s = c->h_jobs[(size_t)n_jobs + k].s;
+            HIP_TRY(launch_dedup(da, st));
+            InitArgs ir = p.init;
+            ir.retrack = 1;
+            HIP_TRY(launch_init(ir, st));
+        }
+        rc = run_pass(false);
+        if (rc != HC_OK) return rc;
+        for (int k = 0; k < n_jobs; k++) {
+            rc = refine_job(k);
+            if (rc != HC_OK) return rc;
+        }
     }
     return HC_OK;
 }
@@ -988,9 +1127,9 @@ hc_status hc_last_profile(hc_ctx *c, hc_profile *out)
     if (!c || !out) return fail(HC_E_INVALID, "hc_last_profile: NULL argument");
     if (!c->profiled_call) return fail(HC_E_INVALID, "hc_last_profile: no profiled call on this context");
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipEventSynchronize(c->ev[5]));
-    float ms[5];
-    for (int i = 0; i < 5; i++) HIP_TRY(hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
+    HIP_TRY(hipEventSynchronize(c->ev[6]));
+    float ms[6];
+    for (int i = 0; i < 6; i++) HIP_TRY(hipEventElapsedTime(&ms[i], c->ev[i], c->ev[i + 1]));
     unsigned long long cnt[2];
     HIP_TRY(hipMemcpy(cnt, static_cast<char *>(c->counter.p) + 16, sizeof cnt, hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof *out);
@@ -999,6 +1138,7 @@ hc_status hc_last_profile(hc_ctx *c, hc_profile *out)
     out->ms_track_fp32 = c->had_fp32 ? ms[2] : 0.0f;
     out->ms_track_fp64 = ms[3];
     out->ms_refine = ms[4];
+    out->ms_crossing = ms[5];
     out->launches_fp32 = c->launches_fp32;
     out->launches_fp64 = c->launches_fp64;
     out->stages_fp32 = (int64_t)cnt[0];

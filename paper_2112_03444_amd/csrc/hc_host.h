@@ -61,7 +61,8 @@ struct DevBuf {
 
 struct hc_system {
     int device = 0;
-    int n = 0, n_terms = 0, n_params = 0, kind = 0, T = 0;
+    int n = 0, n_terms = 0, n_params = 0, kind = 0, T = 0;  // T: table slots per equation
+    int layout = HC_LAYOUT_DENSE;  // HC_LAYOUT_DENSE or HC_LAYOUT_TERMS
     unsigned deg2 = 0;
     int64_t bezout = 0;
     std::vector<int> deg;
@@ -71,6 +72,7 @@ struct hc_system {
     double *d_term_const = nullptr;
     int *d_map_ptr = nullptr, *d_map_col = nullptr;
     double *d_map_val = nullptr;
+    unsigned short *d_vars = nullptr;  // term lists: variables of every slot
 };
 
 struct hc_ctx {
@@ -93,7 +95,7 @@ struct hc_ctx {
     // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
     bool profiling = false;
     bool profiled_call = false;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[7] = {};
     int launches_fp32 = 0, launches_fp64 = 0;
     bool had_fp32 = false;
 };

@@ -24,6 +24,10 @@ __host__ __device__ constexpr int quad_slot(int n, int a, int b)
 // (>= 0) are final; these two mean "still going".
 constexpr int kRunning = -1;  // between launches or at the FP32/FP64 hand-over
 constexpr int kReached = -2;  // at t = 1, waiting for refinement
+constexpr int kDone = -3;     // refined; a re-tracking pass leaves it alone
+constexpr int kRetrack = -4;  // endpoint coincides with another: start over in FP64
+constexpr int kDedupMax = 4096;  // largest n_start the crossing check handles
+constexpr double kCrossTol = 1e-8;  // endpoints this close (relative inf-norm) are one root
 
 // Structure-of-arrays path state in HBM, path index fastest (coalesced when the
 // lanes of a wavefront hold consecutive paths).  x is FP64 in both precisions.
@@ -57,25 +61,46 @@ struct InitArgs {
     const double *start;      // [n_start][n][2] or null (total-degree points)
     double h0;
     TrackState s;
+    int retrack;              // only reset paths marked kRetrack, in FP64 (escal = 1)
+};
+
+// Crossing check after refinement (mixed mode): per instance, a SUCCESS endpoint
+// equal to another one (relative inf-norm distance <= tol) is marked kRetrack;
+// every other path kDone.
+struct DedupArgs {
+    int n, n_start, n_inst;
+    long long total;
+    double tol;
+    const double *endpoints;  // [total][n][2]
+    const int *status;        // [total] final statuses
+    TrackState s;
 };
 
 struct TrackArgs {
     int n;                    // unknowns (the persistent tracker dispatches on it)
     const void *coef;         // [n_inst][n][T][2] in the tracking precision
     const void *coef0;        // parameter homotopy: start tables [n][T][2], else null
+    const double *coef64;     // group tracker in mixed mode: FP64 tables for the FP64 stage
+    const double *coef0_64;   //   and the FP64 start tables of a parameter homotopy
     const double *gamma;      // [n_inst][2] or null (gamma = 1)
     unsigned deg2;
     int n_start, items_per_inst, tracks_per_item, n_items;
     long long total;          // n_inst * n_start: stride of the SoA arrays
-    double t_final;           // 1, or 1 - t_end for the FP32 pass
+    double t_final;           // 1, or 1 - t_end for the FP32 pass (lane tracker)
+    double t_switch;          // group tracker, mixed mode: FP32 -> FP64 at this t (1 - t_end)
+    double tau64;             // group tracker, mixed mode: tolerance of the FP64 stage
     int launch_steps;         // steps per path in this launch, 0 = unlimited
-    int escalate;             // FP32 pass: failures go back to RUNNING for FP64
+    int escalate;             // lane tracker's FP32 pass: failures go back to RUNNING for FP64
     int ir;                   // FP32 pass: FP64 right-hand side in Newton stages
     double h0, h_min, h_max, beta_inc, beta_dec, tau, pred_tol, inf2;
     int n_inc, max_newton, max_steps;
     TrackState s;
     unsigned *n_suspended;    // paths left RUNNING by launch_steps
-    unsigned long long *stage_count;  // or null: stages of active lanes, summed
+    unsigned *head;           // k_track_grp: next work item (zeroed before each launch)
+    const unsigned short *vars;  // term-list layout: [n][n_tslots] variables a | b << 8
+    int n_tslots;             // term-list layout: slots per equation
+    unsigned long long *stage_count;  // or null: stages of active lanes, summed (lane tracker:
+                                      // one counter; group tracker: [FP32, FP64] stages)
 };
 
 struct RefineArgs {
@@ -90,6 +115,9 @@ struct RefineArgs {
     double *endpoints;        // [total][n][2]
     int *status;              // [total]
     hc_track_info *info;      // [total] or null
+    int n;                    // term-list layout: unknowns,
+    int n_tslots;             //   slots per equation
+    const unsigned short *vars;  //   and the slots' variables
 };
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
@@ -113,8 +141,18 @@ int queue_waves(bool fp32, bool param);
 hipError_t launch_fill_u32(unsigned *p, unsigned value, int count, hipStream_t st);
 
 // G lanes per path (one row of [H_x | rhs] per lane); G = group_lanes(n).
-hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, int waves_per_block, hipStream_t st);
+// Persistent grid of resident wavefronts popping a.n_items work items from a.head
+// (which must be zero at launch).
+hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, hipStream_t st);
 int group_lanes(int n);
+
+// Term-list layout (hc_track_terms.hip): 16 lanes per path, n <= 16.
+hipError_t launch_track_terms(bool fp32, const TrackArgs &a, hipStream_t st);
+hipError_t launch_track_queue_terms(bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,
+                                    int n_items, unsigned *head, int n_waves, hipStream_t st);
+int queue_waves_terms(bool fp32, bool param);
+hipError_t launch_refine_terms(const RefineArgs &a, hipStream_t st);
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
+hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
 
 }  // namespace hcx

@@ -388,6 +388,7 @@ __global__ void k_init(const InitArgs a)
     if (g >= a.total) return;
     const long long b = g % a.n_start;
     const TrackState S = a.s;
+    if (a.retrack && S.status[g] != kRetrack) return;
     if (a.start) {
         for (int j = 0; j < a.n; j++) {
             S.xr[j * a.total + g] = a.start[(b * a.n + j) * 2];
@@ -410,11 +411,70 @@ __global__ void k_init(const InitArgs a)
     S.t[g] = 0.0;
     S.h[g] = a.h0;
     S.succ[g] = 0;
-    S.steps[g] = 0;
-    S.rejects[g] = 0;
-    S.nits[g] = 0;
-    S.escal[g] = 0;
+    if (!a.retrack) {
+        S.steps[g] = 0;
+        S.rejects[g] = 0;
+        S.nits[g] = 0;
+    }
+    S.escal[g] = a.retrack ? 1 : 0;
     S.status[g] = kRunning;
+}
+
+// ---------------------------------------------------------------- crossing check
+
+// One block per instance.  Two paths of one instance that end on the same root
+// have crossed (one jumped onto the other's path); both start over in FP64.
+// A complex projection of every SUCCESS endpoint is kept in LDS and compared
+// first; candidates are then compared in full.
+__global__ __launch_bounds__(256) void k_dedup(const DedupArgs a)
+{
+    __shared__ cx<double> proj[kDedupMax];
+    const int inst = blockIdx.x;
+    const long long g0 = (long long)inst * a.n_start;
+    const TrackState S = a.s;
+    const bool check = a.n_start <= kDedupMax;
+    for (int b = threadIdx.x; check && b < a.n_start; b += blockDim.x) {
+        const long long g = g0 + b;
+        cx<double> p = {NAN, NAN};
+        if (a.status[g] == HC_T_SUCCESS) {
+            p = {0.0, 0.0};
+            for (int j = 0; j < a.n; j++) {
+                const cx<double> w = {cos(1.3 * j + 0.4), sin(2.1 * j + 0.9)};  // fixed generic weights
+                p = cfma(w, cx<double>{a.endpoints[(g * a.n + j) * 2], a.endpoints[(g * a.n + j) * 2 + 1]}, p);
+            }
+        }
+        proj[b] = p;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < a.n_start; b += blockDim.x) {
+        const long long g = g0 + b;
+        bool dup = false;
+        if (check && a.status[g] == HC_T_SUCCESS) {
+            const cx<double> pb = proj[b];
+            const double pre = 1e-6 * (1.0 + sqrt(abs2(pb)));
+            for (int c = 0; c < a.n_start && !dup; c++) {
+                const cx<double> pc = proj[c];
+                if (c == b || !(fabs(pc.re - pb.re) + fabs(pc.im - pb.im) <= pre)) continue;
+                const long long h = g0 + c;
+                double dmax = 0.0, cmax = 0.0;
+                for (int j = 0; j < a.n; j++) {
+                    const double xr = a.endpoints[(g * a.n + j) * 2], xi = a.endpoints[(g * a.n + j) * 2 + 1];
+                    const double yr = a.endpoints[(h * a.n + j) * 2], yi = a.endpoints[(h * a.n + j) * 2 + 1];
+                    dmax = fmax(dmax, sqrt((xr - yr) * (xr - yr) + (xi - yi) * (xi - yi)));
+                    cmax = fmax(cmax, sqrt(yr * yr + yi * yi));
+                }
+                dup = dmax <= a.tol * fmax(1.0, cmax);
+            }
+        }
+        S.status[g] = dup ? kRetrack : kDone;
+    }
+}
+
+hipError_t launch_dedup(const DedupArgs &a, hipStream_t st)
+{
+    if (a.total == 0 || a.n_inst == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dedup, dim3((unsigned)a.n_inst), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- prep (a0/a2)
@@ -517,6 +577,7 @@ __global__ __launch_bounds__(256) void k_refine(const RefineArgs a)
     if (a.gamma) gam = {a.gamma[2 * inst], a.gamma[2 * inst + 1]};
     const TrackState S = a.s;
     int st = valid ? S.status[g] : HC_T_SUCCESS;
+    const bool done = st == kDone;  // final from an earlier pass: nothing to write
     cx<double> x[N];
 #pragma unroll
     for (int j = 0; j < N; j++) x[j] = {S.xr[j * a.total + g], S.xi[j * a.total + g]};
@@ -548,7 +609,7 @@ __global__ __launch_bounds__(256) void k_refine(const RefineArgs a)
             }
         }
     }
-    if (!valid) return;
+    if (!valid || done) return;
     if (st == kReached) {
         bool fin = true;
         double big = 0.0;

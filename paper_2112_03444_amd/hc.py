@@ -22,7 +22,8 @@ HC_FP64, HC_MIXED = 0, 1
  HC_T_REFINE_FAILED) = range(7)
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
                 "REFINE_FAILED"]
-HC_MAX_N = 8
+HC_MAX_N = 16
+HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
 
 
 class HcError(RuntimeError):
@@ -59,11 +60,11 @@ class Profile(ctypes.Structure):
     _fields_ = [(k, ctypes.c_float) for k in
                 ("ms_prep", "ms_init", "ms_track_fp32", "ms_track_fp64", "ms_refine")] + \
                [("launches_fp32", ctypes.c_int32), ("launches_fp64", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stages_fp32", ctypes.c_int64),
+                ("ms_crossing", ctypes.c_float), ("stages_fp32", ctypes.c_int64),
                 ("stages_fp64", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 INFO_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_its", np.int32),
@@ -99,6 +100,8 @@ def lib():
         L.hc_destroy.argtypes = [P]
         L.hc_load_system.restype = ctypes.c_int
         L.hc_load_system.argtypes = [P, ctypes.POINTER(SystemDesc), ctypes.POINTER(P)]
+        L.hc_load_system_layout.restype = ctypes.c_int
+        L.hc_load_system_layout.argtypes = [P, ctypes.POINTER(SystemDesc), I32, ctypes.POINTER(P)]
         L.hc_free_system.restype = ctypes.c_int
         L.hc_free_system.argtypes = [P, P]
         L.hc_system_dims.restype = ctypes.c_int
@@ -202,9 +205,11 @@ class Context:
         except Exception:
             pass
 
-    def load_system(self, system, kind: int = HC_TOTAL_DEGREE, coef_const=None, coef_map=None) -> System:
+    def load_system(self, system, kind: int = HC_TOTAL_DEGREE, coef_const=None, coef_map=None,
+                    layout: int = HC_LAYOUT_AUTO) -> System:
         """system: object with n, term_eq [n_terms], term_exp [n_terms, n].
-        coef_map: None (identity, p = coefficients) or (rowptr, col, val) CSR."""
+        coef_map: None (identity, p = coefficients) or (rowptr, col, val) CSR.
+        layout: HC_LAYOUT_AUTO, HC_LAYOUT_DENSE or HC_LAYOUT_TERMS."""
         te = np.ascontiguousarray(system.term_eq, np.int32)
         tx = np.ascontiguousarray(system.term_exp, np.int32)
         keep = [te, tx]
@@ -231,7 +236,7 @@ class Context:
             d.coef_col = col.ctypes.data if col.size else None
             d.coef_val = val.ctypes.data if val.size else None
         h = ctypes.c_void_p()
-        _check(lib().hc_load_system(self.handle, ctypes.byref(d), ctypes.byref(h)))
+        _check(lib().hc_load_system_layout(self.handle, ctypes.byref(d), int(layout), ctypes.byref(h)))
         del keep
         s = System(self, h)
         self._systems.append(s)

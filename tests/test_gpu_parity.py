@@ -217,9 +217,13 @@ def test_path_at_infinity(hc, ctx):
 
 
 def test_load_system_errors(hc, ctx):
-    S9 = hc_inputs.dense_quadratic_system(9)
+    S17 = hc_inputs.dense_quadratic_system(17)
     with pytest.raises(hc.HcError):
-        ctx.load_system(S9)  # n > HC_MAX_N
+        ctx.load_system(S17)  # n > HC_MAX_N
+    with pytest.raises(hc.HcError):
+        ctx.load_system(hc_inputs.dense_quadratic_system(9), layout=hc.HC_LAYOUT_DENSE)  # dense tables: n <= 8
+    with pytest.raises(hc.HcError):
+        ctx.load_system(hc_inputs.dense_quadratic_system(3), layout=7)
     cubic = hc_inputs.PolySystem(n=1, term_eq=np.array([0], np.int32), term_exp=np.array([[3]], np.int32))
     with pytest.raises(hc.HcError):
         ctx.load_system(cubic)
