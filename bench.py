@@ -49,6 +49,21 @@ def w_stage(n: int) -> int:
     return w_eval(n) + w_lu(n)
 
 
+def w_eval_terms(system, param: bool) -> int:
+    """Algorithmic FLOPs of one evaluation of [H_x | rhs] from term lists, per
+    term: blend of the coefficient (parameter homotopy: 6, and 2 for the
+    right-hand side's c1 - c0), the monomial (6 for two factors), F += c m (8),
+    and the Jacobian entries (8 per factor of a degree-2 term, an add for a
+    linear one).  Total degree adds 37 per equation for G, gamma and the blend."""
+    deg = np.asarray(system.term_exp).sum(axis=1)
+    blend = 8 if param else 0
+    per = {0: blend + 2, 1: blend + 8 + 2, 2: blend + 6 + 8 + 16}
+    w = int(sum(per[int(d)] for d in deg))
+    if not param:
+        w += 37 * int(system.n)
+    return w
+
+
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -67,7 +82,7 @@ def time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch):
     return (t1 - t0) / steps, profs
 
 
-def roofline(profs, n, kind):
+def roofline(profs, n, kind, flops_per_stage=None, kernel=None):
     """Tracker launches of one mode.  The mixed-precision tracker is one launch of
     k_track_grp<.., float, ..> whose escalated paths run their FP64 stages inside
     the same launch, so both stage counts go to that launch."""
@@ -75,15 +90,16 @@ def roofline(profs, n, kind):
     ms = float(np.mean([p[f"ms_track_{key}"] for p in profs]))
     launches = float(np.mean([p[f"launches_{key}"] for p in profs]))
     stages = float(np.mean([p[f"stages_{key}"] + (p["stages_fp64"] if key == "fp32" else 0.0) for p in profs]))
-    flops = stages * w_stage(n)
+    wst = flops_per_stage if flops_per_stage is not None else w_stage(n)
+    flops = stages * wst
     per_launch_ms = ms / max(launches, 1.0)
     achieved = flops / launches / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[key]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>",
+            "kernel": kernel or f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>",
             "kernel_ms_per_launch": round(per_launch_ms, 4), "launches_per_step": launches,
-            "stages_per_launch": stages / launches, "flops_per_stage": w_stage(n)}
+            "stages_per_launch": stages / launches, "flops_per_stage": wst}
 
 
 def cpu_baseline(S, coef, gam, budget_s=12.0):
@@ -102,37 +118,93 @@ def cpu_baseline(S, coef, gam, budget_s=12.0):
                       f"{threads} threads; success {np.mean(ost == 0):.4f}"}
 
 
-def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5):
+def vision_leg(ctx, hc, torch, steps, warmup):
+    """4-view triangulation batch (4096 instances x 296 paths, parameter homotopy
+    from the monodromy start set) in both precisions."""
+    import hc_inputs.vision as V
+    dev = torch.device("cuda:0")
+    S = V.triangulation_system()
+    c0, sols = V.start_instance()
+    _, coef, _ = V.vision_workload("triang4_batch4096")
+    n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
+    p = torch.from_numpy(coef).to(dev)
+    ps = torch.from_numpy(c0).to(dev)
+    start = torch.from_numpy(sols).to(dev)
+    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    wst = w_eval_terms(S, True) + w_lu(n)
+    out = {"workload": "triang4_batch4096: 4096 noisy 4-view triangulation instances (n=14, 134 terms), "
+                       "parameter homotopy from a 296-solution monodromy start set (1,212,416 paths)"}
+    for mode in ("fp64", "mixed"):
+        opts = hc.default_opts(precision=mode)
+        for _ in range(warmup):
+            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
+        torch.cuda.synchronize()
+        profs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
+            profs.append(ctx.last_profile().as_dict())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        stn = st.cpu().numpy()
+        inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
+                     "escalated": int(inf["escalated"].sum()),
+                     "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
+                     "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
+                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
+                                          f"k_track_terms<{'float' if mode == 'mixed' else 'double'},true>")}
+        log(f"bench: triangulation {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
+    out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
+    return out
+
+
+def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="mixed"):
     """Open-loop Poisson arrivals at `rate` requests/s into the serving loop.
-    Mix: 60% one dense n = 8 system with 256 paths (the throughput workload's
-    request), 40% one dense system with n uniform in 5..8 and 2^n paths."""
+    Mix: 40% one dense n = 8 system with 256 paths (the throughput workload's
+    request), 40% one 4-view triangulation instance (296 paths from the resident
+    start set), 20% one dense system with n uniform in 5..10 and 2^n paths."""
     import hc_inputs
+    import hc_inputs.vision as V
     rng = np.random.default_rng(seed)
-    systems = {n: ctx.load_system(hc_inputs.dense_quadratic_system(n)) for n in range(5, 9)}
-    pool = {n: hc_inputs.dense_quadratic_instances(n, 64, seed=900 + n) for n in range(5, 9)}
-    srv = hc.Server(ctx, max_inflight=3, max_batch_requests=64, opts=hc.default_opts(precision="mixed"))
+    systems = {n: ctx.load_system(hc_inputs.dense_quadratic_system(n)) for n in range(5, 11)}
+    pool = {n: hc_inputs.dense_quadratic_instances(n, 64, seed=900 + n) for n in range(5, 11)}
+    tri = ctx.load_system(V.triangulation_system(), kind=hc.HC_PARAMETER)
+    tri_c0, tri_sols = V.start_instance()
+    _, tri_coef, _ = V.triangulation_instances(64, seed=950)
+    srv = hc.Server(ctx, max_inflight=4, max_batch_requests=256, opts=hc.default_opts(precision=precision))
     total = warm_s + meas_s
     gaps = rng.exponential(1.0 / rate, size=int(rate * total * 1.2) + 16)
     arrivals = np.cumsum(gaps)
     arrivals = arrivals[arrivals < total]
     kinds = rng.random(len(arrivals))
-    ns = rng.integers(5, 9, size=len(arrivals))
+    ns = rng.integers(5, 11, size=len(arrivals))
     picks = rng.integers(0, 64, size=len(arrivals))
     tickets = []
     reset_done = False
     t0 = time.perf_counter()
     paths = 0
     for k, ta in enumerate(arrivals):
-        n = 8 if kinds[k] < 0.6 else int(ns[k])
-        _, coef, gam = pool[n]
         while time.perf_counter() - t0 < ta:
             pass
         if not reset_done and ta >= warm_s:
             srv.reset_stats()
             reset_done = True
-        tickets.append(srv.submit(systems[n], coef[picks[k]], gam[picks[k]]))
+        if 0.4 <= kinds[k] < 0.8:
+            tickets.append(srv.submit(tri, tri_coef[picks[k]], start=tri_sols, p_start=tri_c0))
+            npaths = tri_sols.shape[0]
+        else:
+            n = 8 if kinds[k] < 0.4 else int(ns[k])
+            _, coef, gam = pool[n]
+            tickets.append(srv.submit(systems[n], coef[picks[k]], gam[picks[k]]))
+            npaths = 2 ** n
         if ta >= warm_s:
-            paths += 2 ** n
+            paths += npaths
     for t in tickets:
         srv.wait(t)
     st = srv.stats()
@@ -141,7 +213,8 @@ def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5):
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
             "solves_per_s": round(st["completed"] / st["wall_s"], 1),
             "tracks_per_s": round(st["tracks_completed"] / st["wall_s"], 1), "batches": int(st["batches"]),
-            "mix": "60% dense n=8 (256 paths), 40% dense n in 5..8 (2^n paths); mixed precision"}
+            "mix": "40% dense n=8 (256 paths), 40% 4-view triangulation (296 paths), 20% dense n in 5..10 "
+                   f"(2^n paths); {precision} precision; 4 batches in flight, <= 256 requests per batch"}
 
 
 def main():
@@ -247,8 +320,13 @@ def main():
         extras["latency_dense3_single_graph_ms"] = {"p50": float(np.percentile(lat, 50)),
                                                     "p99": float(np.percentile(lat, 99)),
                                                     "repeats": len(lat)}
-        log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s")
+        log("bench: 4-view triangulation batch")
+        ctx.set_profiling(True)
+        extras["triangulation"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
+        ctx.set_profiling(False)
+        log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
         extras["serving"] = serve_mix(ctx, hc)
+        extras["serving_fp64"] = serve_mix(ctx, hc, precision="fp64")
 
     cpu = None
     if not args.no_cpu:

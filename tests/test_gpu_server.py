@@ -63,6 +63,36 @@ def test_alone_equals_in_the_mix(hc, ctx):
     srv.close()
 
 
+def test_vision_and_large_requests_in_the_mix(hc, ctx):
+    """Term-list requests (4-view triangulation parameter homotopies with their
+    start points, n = 10 total degree) interleaved with dense n = 8 requests:
+    each result equals the same request tracked alone."""
+    import hc_inputs.vision as V
+    opts = hc.default_opts(precision="mixed")
+    tri = ctx.load_system(V.triangulation_system(), kind=hc.HC_PARAMETER)
+    c0, sols = V.start_instance()
+    _, tcoef, _ = V.triangulation_instances(4, seed=6100)
+    s8 = ctx.load_system(hc_inputs.dense_quadratic_system(8))
+    s10 = ctx.load_system(hc_inputs.dense_quadratic_system(10))
+    srv = hc.Server(ctx, max_inflight=3, max_batch_requests=8, opts=opts)
+    reqs = []
+    for k in range(4):
+        reqs.append(("tri", tcoef[k:k + 1], srv.submit(tri, tcoef[k:k + 1], start=sols, p_start=c0)))
+        _, c8, g8 = hc_inputs.dense_quadratic_instances(8, 1, seed=6200 + k)
+        reqs.append(("d8", (c8, g8), srv.submit(s8, c8, g8)))
+    _, c10, g10 = hc_inputs.dense_quadratic_instances(10, 1, seed=6300)
+    reqs.append(("d10", (c10, g10), srv.submit(s10, c10, g10)))
+    for kind, data, t in reqs:
+        ep, st, _ = srv.wait(t)
+        if kind == "tri":
+            rep, rst, _ = ctx.track(tri, data, start=sols, p_start=c0, opts=opts)
+        else:
+            rep, rst, _ = ctx.track(s8 if kind == "d8" else s10, data[0], data[1], opts=opts)
+        np.testing.assert_array_equal(ep, rep)
+        np.testing.assert_array_equal(st, rst)
+    srv.close()
+
+
 def test_tight_budget_still_completes(hc, ctx):
     opts = hc.default_opts(precision="fp64")
     sysh = ctx.load_system(hc_inputs.dense_quadratic_system(7))
