@@ -27,6 +27,10 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
+# HBM bytes per tracking launch on dense8_batch512 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# calibrated on a 512 MiB device copy (profiles/k_track_grp_dense8_batch512.md); they belong to
+# the kernel version profiled there and are not measured live.
+PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 146.9e6, "k_track_grp<8,8,double,false>": 335.9e6}
 SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
 
@@ -95,9 +99,10 @@ def roofline(profs, n, kind, flops_per_stage=None, kernel=None):
     per_launch_ms = ms / max(launches, 1.0)
     achieved = flops / launches / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[key]
+    kname = kernel or f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>"
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": kernel or f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>",
+            "frac": round(achieved / peak, 4), "traffic": PROFILED_TRAFFIC_BYTES.get(kname),
+            "kernel": kname,
             "kernel_ms_per_launch": round(per_launch_ms, 4), "launches_per_step": launches,
             "stages_per_launch": stages / launches, "flops_per_stage": wst}
 
@@ -225,7 +230,12 @@ def main():
     ap.add_argument("--mode", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the per-instance FP64 comparator and the latency run")
+                    help="skip every leg beyond the dense8_batch512 batch")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a known-size kernel that calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters in a profiled run)")
+    ap.add_argument("--skip", default="",
+                    help="comma-separated legs to skip: per_instance,latency,triangulation,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -239,6 +249,13 @@ def main():
     import paper_2112_03444_amd as hc
 
     dev = torch.device("cuda:0")
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mib} MiB device to device")
+        del src, dst
     S, coef, gam = hc_inputs.workload("dense8_batch512")
     n_inst, n_start, n = coef.shape[0], 256, S.n
     p = torch.from_numpy(coef).to(dev)
@@ -271,7 +288,8 @@ def main():
         log(f"bench: {mode}: {dt * 1e3:.2f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
 
     extras = {}
-    if not args.no_extras:
+    skip = set(x for x in args.skip.split(",") if x)
+    if not args.no_extras and "per_instance" not in skip:
         # paper-style comparator: plain FP64, one instance per call (one launch set each)
         log("bench: per-instance FP64 comparator (512 calls)")
         o64 = hc.default_opts(precision="fp64")
@@ -284,6 +302,9 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         extras["per_instance_fp64"] = {"tracks_per_s": n_inst * n_start / dt, "ms_per_instance": dt / n_inst * 1e3}
+    if not args.no_extras and "latency" not in skip:
+        o64 = hc.default_opts(precision="fp64")
+        ctx.set_profiling(False)
         # latency of one small instance (n = 3, 8 paths, FP64)
         log("bench: single-instance latency (n=3, 8 paths, FP64), 1000 calls")
         S1, c1, g1 = hc_inputs.workload("dense3_single")
@@ -320,10 +341,12 @@ def main():
         extras["latency_dense3_single_graph_ms"] = {"p50": float(np.percentile(lat, 50)),
                                                     "p99": float(np.percentile(lat, 99)),
                                                     "repeats": len(lat)}
+    if not args.no_extras and "triangulation" not in skip:
         log("bench: 4-view triangulation batch")
         ctx.set_profiling(True)
         extras["triangulation"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
         ctx.set_profiling(False)
+    if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
         extras["serving"] = serve_mix(ctx, hc)
         extras["serving_fp64"] = serve_mix(ctx, hc, precision="fp64")

@@ -136,6 +136,10 @@ typedef struct {
     int32_t fp64_residual;    /* mixed mode: the FP32 pass's Newton corrector evaluates
                                  H(x, t) in FP64 at an FP64 point and solves with the
                                  FP32 LU (iterative refinement)                  (0)     */
+    int32_t crossing_check;   /* mixed mode: after refinement, paths of one instance
+                                 that ended on the same root (relative distance
+                                 <= 1e-8; n_start <= 4096) start over in FP64    (1)     */
+    int32_t reserved;
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;

@@ -81,6 +81,7 @@ void hc_default_opts(hc_opts *o)
     o->tracks_per_item = 0;
     o->lanes_per_path = 0;
     o->fp64_residual = 0;
+    o->crossing_check = 1;
 }
 
 const char *hc_last_error(void) { return last_error(); }
@@ -582,7 +583,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         }
         return HC_OK;
     };
-    if (lanes > 1 && mixed) {
+    if (lanes > 1 && mixed && kInlineEsc) {
         // group tracker: one launch; failed paths and the end zone go on in FP64
         // inside the kernel
         rc = run_pass(true, 1.0, 0);
@@ -590,8 +591,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         c->had_fp32 = true;
         if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
     } else {
-        // lane tracker: an FP32 pass to 1 - t_end that hands its failures back,
-        // then the FP64 pass
+        // an FP32 pass to 1 - t_end that hands its failures back, then the FP64
+        // pass
         if (mixed) {
             rc = run_pass(true, 1.0 - o.t_end, 1);
             if (rc != HC_OK) return rc;
@@ -623,7 +624,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
     else HIP_TRY(launch_refine(n, ra, st));
     if (prof) HIP_TRY(hipEventRecord(c->ev[5], st));
-    if (mixed) {
+    if (mixed && o.crossing_check) {
         // crossing check: paths that ended on the same root start over in FP64
         DedupArgs da;
         da.n = n;
@@ -984,10 +985,11 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             ta.items_per_inst = (p.j->n_start + p.tpi - 1) / p.tpi;
             ta.n_items = ta.items_per_inst * p.j->n_inst;
             ta.total = p.total;
-            // one launch in mixed mode: the FP32 tracker goes on in FP64 in-kernel
+            // in-kernel escalation: one launch in mixed mode, the FP32 tracker goes
+            // on in FP64; otherwise an FP32 pass to 1 - t_end and an FP64 pass
             ta.coef64 = t64;
             ta.coef0_64 = t64s;
-            ta.t_final = 1.0;
+            ta.t_final = (fp32 && !kInlineEsc) ? 1.0 - o.t_end : 1.0;
             ta.t_switch = fp32 ? 1.0 - o.t_end : 1.0;
             ta.tau64 = o.tau64;
             ta.launch_steps = 0;
@@ -1054,6 +1056,10 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     };
     rc = run_pass(mixed);
     if (rc != HC_OK) return rc;
+    if (mixed && !kInlineEsc) {
+        rc = run_pass(false);
+        if (rc != HC_OK) return rc;
+    }
     auto refine_job = [&](int k) -> hc_status {
         const Plan &p = plan[k];
         if (p.total == 0) return HC_OK;
@@ -1083,7 +1089,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         rc = refine_job(k);
         if (rc != HC_OK) return rc;
     }
-    if (mixed) {
+    if (mixed && o.crossing_check) {
         // crossing check per job, then one FP64 pass over the queues and the
         // refinement of the re-tracked paths
         for (int k = 0; k < n_jobs; k++) {

@@ -770,11 +770,16 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     };
     auto fail = [&](int st) {
         if (!R64 && !p64 && st != HC_T_AT_INFINITY) {
-            // mixed precision: the path goes on in FP64 from its last accepted point
-            p64 = true;
+            // mixed precision: the path goes on in FP64 from its last accepted point,
+            // in this launch or (escalation off) in the FP64 launch that follows
             escal = 1;
             h = a.h0;
             succ = 0;
+            if (!kInlineEsc) {
+                save(kRunning);
+                return;
+            }
+            p64 = true;
             if (steps + rejects >= a.max_steps)
                 save(HC_T_MAX_STEPS);
             else
@@ -808,7 +813,8 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
             if (trk < 0 && cand < tend) {
                 const long long gg = (long long)cur_inst * a.n_start + cand;
                 // still going and not yet at this launch's end time
-                if (S.status[gg] == kRunning && S.t[gg] < a.t_final) {
+                if (S.status[gg] == kRunning && S.t[gg] < a.t_final &&
+                    (R64 || kInlineEsc || S.escal[gg] == 0)) {
                     trk = cand;
                     g = gg;
                     gslot = cur_slot;
@@ -827,7 +833,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     rejects = S.rejects[g];
                     nits = S.nits[g];
                     escal = S.escal[g];
-                    p64 = R64 || escal != 0 || t >= a.t_switch;
+                    p64 = R64 || (kInlineEsc && (escal != 0 || t >= a.t_switch));
                     lsteps = 0;
                     if (steps + rejects >= a.max_steps)
                         fail(HC_T_MAX_STEPS);
@@ -861,7 +867,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 sing = stage_solve<N, G, R, PARAM>(LdsRow<N, R>{cl}, p0, p1, r, base, d2, gam, gam64, xe, te, pred,
                                                    ir, d, nd2);
         }
-        if constexpr (!R64) {
+        if constexpr (!R64 && kInlineEsc) {
             if (ballot(act && p64) != 0ull) {
                 const double *q0 = row0_64, *q1 = row1_64;
                 asm volatile("" : "+v"(q0), "+v"(q1));

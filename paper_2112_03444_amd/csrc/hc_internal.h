@@ -27,6 +27,14 @@ constexpr int kReached = -2;  // at t = 1, waiting for refinement
 constexpr int kDone = -3;     // refined; a re-tracking pass leaves it alone
 constexpr int kRetrack = -4;  // endpoint coincides with another: start over in FP64
 constexpr int kDedupMax = 4096;  // largest n_start the crossing check handles
+
+// Mixed precision on the group trackers: 1 = a failed FP32 path goes on in FP64
+// inside the same launch; 0 = it goes back to RUNNING and a second (FP64) launch
+// takes it over.
+#ifndef HC_INLINE_ESCALATION
+#define HC_INLINE_ESCALATION 1
+#endif
+constexpr bool kInlineEsc = HC_INLINE_ESCALATION != 0;
 constexpr double kCrossTol = 1e-8;  // endpoints this close (relative inf-norm) are one root
 
 // Structure-of-arrays path state in HBM, path index fastest (coalesced when the

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                  "tau_refine", "inf_bound", "eta_max", "t_end")] + \
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
-                 "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual")]
+                 "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual",
+                 "crossing_check", "reserved")]
 
 
 class Job(ctypes.Structure):

@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(hc):
 
 
 def test_struct_layouts_match_header(hc):
-    assert ctypes.sizeof(hc.Opts) == 12 * 8 + 10 * 4
+    assert ctypes.sizeof(hc.Opts) == 12 * 8 + 12 * 4
     assert hc.INFO_DTYPE.itemsize == 32
     assert ctypes.sizeof(hc.hc.SystemDesc) == 4 * 2 + 8 * 2 + 4 * 2 + 8 * 4
 
@@ -53,6 +53,7 @@ def test_default_opts(hc):
     assert (o.inf_bound, o.eta_max, o.t_end) == (1e7, 1e-10, 0.0)
     assert (o.n_inc, o.max_newton, o.max_steps, o.max_refine) == (5, 3, 5000, 10)
     assert o.precision == hc.HC_FP64 and o.steps_per_launch == 0 and o.fp64_residual == 0
+    assert o.crossing_check == 1
 
 
 def test_paper_term_table_example(hc):
