@@ -113,7 +113,7 @@ typedef struct {
     double beta_inc;    /* growth factor after n_inc consecutive accepts       (2)     */
     double beta_dec;    /* factor applied on a rejected step                   (0.5)   */
     double tau64;       /* FP64 corrector: ||dx||_2 <= tau (1 + ||x||_2)      (1e-6)  */
-    double tau32;       /* FP32 corrector tolerance in mixed mode              (1e-4)  */
+    double tau32;       /* FP32 corrector tolerance in mixed mode              (3e-4)  */
     double pred_tol;    /* first correction above pred_tol (1 + ||x||_2)
                            rejects the step (prediction too far off)          (1e-2)  */
     double tau_refine;  /* refinement stops when ||dx||_2 <= tau_refine (1+||x||_2) (1e-14) */

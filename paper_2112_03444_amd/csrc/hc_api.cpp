@@ -66,7 +66,7 @@ void hc_default_opts(hc_opts *o)
     o->beta_inc = 2.0;
     o->beta_dec = 0.5;
     o->tau64 = 1e-6;
-    o->tau32 = 1e-4;
+    o->tau32 = 3e-4;
     o->pred_tol = 1e-2;
     o->tau_refine = 1e-14;
     o->inf_bound = 1e7;

@@ -49,7 +49,7 @@ def test_struct_layouts_match_header(hc):
 def test_default_opts(hc):
     o = hc.default_opts()
     assert (o.h0, o.h_min, o.h_max, o.beta_inc, o.beta_dec) == (0.05, 1e-7, 0.1, 2.0, 0.5)
-    assert (o.tau64, o.tau32, o.pred_tol, o.tau_refine) == (1e-6, 1e-4, 1e-2, 1e-14)
+    assert (o.tau64, o.tau32, o.pred_tol, o.tau_refine) == (1e-6, 3e-4, 1e-2, 1e-14)
     assert (o.inf_bound, o.eta_max, o.t_end) == (1e7, 1e-10, 0.0)
     assert (o.n_inc, o.max_newton, o.max_steps, o.max_refine) == (5, 3, 5000, 10)
     assert o.precision == hc.HC_FP64 and o.steps_per_launch == 0 and o.fp64_residual == 0
