@@ -909,6 +909,10 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
 
     // job descriptors (one set per pass) and the two queues (total degree, parameter)
     c->h_jobs.assign((size_t)2 * n_jobs, TrackArgs{});
+    // per-job arguments of the steps around tracking, launched once for all jobs
+    std::vector<PrepArgs> preps;
+    std::vector<InitArgs> inits;
+    long long max_prep = 0, max_total = 0;
     // queues: [dense | term lists] x [total degree | parameter]
     std::vector<QueueItem> qs[4];
     std::vector<int> job_n(n_jobs);
@@ -951,14 +955,15 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         pa.params = reinterpret_cast<const double *>(p.j->p_target);
         pa.out64 = t64;
         pa.out32 = t32;
-        HIP_TRY(launch_prep(pa, st));
+        preps.push_back(pa);
+        max_prep = std::max(max_prep, (long long)pa.n_inst * pa.n_slots);
         if (p.param) {
             PrepArgs p0 = pa;
             p0.n_inst = 1;
             p0.params = reinterpret_cast<const double *>(p.j->p_start);
             p0.out64 = const_cast<double *>(t64s);
             p0.out32 = const_cast<float *>(t32s);
-            HIP_TRY(launch_prep(p0, st));
+            preps.push_back(p0);
         }
         InitArgs ia;
         ia.n = p.n;
@@ -969,7 +974,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ia.h0 = o.h0;
         ia.s = S;
         ia.retrack = 0;
-        HIP_TRY(launch_init(ia, st));
+        inits.push_back(ia);
+        max_total = std::max(max_total, p.total);
         p.init = ia;
 
         for (int pass = 0; pass < 2; pass++) {
@@ -1026,43 +1032,16 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         c->h_items.insert(c->h_items.end(), qs[qi].begin(), qs[qi].end());
         q_off[qi + 1] = (int)c->h_items.size();
     }
-    const size_t b_jobs = al(c->h_jobs.size() * sizeof(TrackArgs));
-    const size_t b_items = al(std::max<size_t>(c->h_items.size(), 1) * sizeof(QueueItem));
-    HIP_TRY(c->queue.ensure(b_jobs + b_items + 256));
-    char *qb = static_cast<char *>(c->queue.p);
-    TrackArgs *d_jobs = reinterpret_cast<TrackArgs *>(qb);
-    QueueItem *d_items = reinterpret_cast<QueueItem *>(qb + b_jobs);
-    unsigned *heads = reinterpret_cast<unsigned *>(qb + b_jobs + b_items);
-    if (n_jobs > 0)
-        HIP_TRY(hipMemcpyAsync(d_jobs, c->h_jobs.data(), c->h_jobs.size() * sizeof(TrackArgs), hipMemcpyHostToDevice, st));
-    if (!c->h_items.empty())
-        HIP_TRY(hipMemcpyAsync(d_items, c->h_items.data(), c->h_items.size() * sizeof(QueueItem),
-                               hipMemcpyHostToDevice, st));
-    auto run_pass = [&](bool fp32) -> hc_status {
-        const TrackArgs *pj = d_jobs + (fp32 ? 0 : n_jobs);
-        HIP_TRY(launch_fill_u32(heads, 0u, 4, st));
-        for (int qi = 0; qi < 4; qi++) {
-            const int cnt = q_off[qi + 1] - q_off[qi];
-            if (cnt == 0) continue;
-            const bool param = (qi & 1) != 0;
-            if (qi < 2)
-                HIP_TRY(launch_track_queue(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
-                                           queue_waves(fp32, param), st));
-            else
-                HIP_TRY(launch_track_queue_terms(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
-                                                 queue_waves_terms(fp32, param), st));
-        }
-        return HC_OK;
-    };
-    rc = run_pass(mixed);
-    if (rc != HC_OK) return rc;
-    if (mixed && !kInlineEsc) {
-        rc = run_pass(false);
-        if (rc != HC_OK) return rc;
-    }
-    auto refine_job = [&](int k) -> hc_status {
+    // refinement, crossing-check and re-tracking arguments per job; refinement
+    // launches once per dense n and once for the term lists
+    std::vector<RefineArgs> refs[kMaxN + 2];  // [n] dense, [kMaxN + 1] term lists
+    std::vector<DedupArgs> dedups;
+    std::vector<InitArgs> retracks;
+    long long ref_items[kMaxN + 2] = {};
+    int max_inst = 0;
+    for (int k = 0; k < n_jobs; k++) {
         const Plan &p = plan[k];
-        if (p.total == 0) return HC_OK;
+        if (p.total == 0) continue;
         const TrackArgs &ta = c->h_jobs[(size_t)n_jobs + k];
         RefineArgs ra;
         ra.coef = static_cast<const double *>(ta.coef);
@@ -1081,40 +1060,108 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ra.n = p.n;
         ra.n_tslots = p.s->T;
         ra.vars = p.s->d_vars;
-        if (p.s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
-        else HIP_TRY(launch_refine(p.n, ra, st));
+        const int rk = p.s->layout == HC_LAYOUT_TERMS ? kMaxN + 1 : p.n;
+        refs[rk].push_back(ra);
+        ref_items[rk] = std::max(ref_items[rk], rk == kMaxN + 1 ? p.total
+                                                                : (long long)p.j->n_inst * ((p.j->n_start + 63) / 64));
+        DedupArgs da;
+        da.n = p.n;
+        da.n_start = p.j->n_start;
+        da.n_inst = p.j->n_inst;
+        da.total = p.total;
+        da.tol = kCrossTol;
+        da.endpoints = reinterpret_cast<const double *>(p.j->endpoints);
+        da.status = p.j->status;
+        da.s = ta.s;
+        dedups.push_back(da);
+        max_inst = std::max(max_inst, p.j->n_inst);
+        InitArgs ir = p.init;
+        ir.retrack = 1;
+        retracks.push_back(ir);
+    }
+
+    // one upload: job descriptors, work items, per-step argument arrays, queue heads
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = off;
+        off += al(std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t o_jobs = place(c->h_jobs.size() * sizeof(TrackArgs));
+    const size_t o_items = place(c->h_items.size() * sizeof(QueueItem));
+    const size_t o_prep = place(preps.size() * sizeof(PrepArgs));
+    const size_t o_init = place(inits.size() * sizeof(InitArgs));
+    const size_t o_dedup = place(dedups.size() * sizeof(DedupArgs));
+    const size_t o_retr = place(retracks.size() * sizeof(InitArgs));
+    size_t o_ref[kMaxN + 2];
+    for (int rk = 0; rk < kMaxN + 2; rk++) o_ref[rk] = place(refs[rk].size() * sizeof(RefineArgs));
+    const size_t o_heads = place(4 * sizeof(unsigned));
+    c->h_blob.assign(off, 0);
+    auto put_arr = [&](size_t at, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(c->h_blob.data() + at, src, bytes);
+    };
+    put_arr(o_jobs, c->h_jobs.data(), c->h_jobs.size() * sizeof(TrackArgs));
+    put_arr(o_items, c->h_items.data(), c->h_items.size() * sizeof(QueueItem));
+    put_arr(o_prep, preps.data(), preps.size() * sizeof(PrepArgs));
+    put_arr(o_init, inits.data(), inits.size() * sizeof(InitArgs));
+    put_arr(o_dedup, dedups.data(), dedups.size() * sizeof(DedupArgs));
+    put_arr(o_retr, retracks.data(), retracks.size() * sizeof(InitArgs));
+    for (int rk = 0; rk < kMaxN + 2; rk++) put_arr(o_ref[rk], refs[rk].data(), refs[rk].size() * sizeof(RefineArgs));
+    HIP_TRY(c->queue.ensure(off));
+    char *qb = static_cast<char *>(c->queue.p);
+    HIP_TRY(hipMemcpyAsync(qb, c->h_blob.data(), o_heads, hipMemcpyHostToDevice, st));
+    TrackArgs *d_jobs = reinterpret_cast<TrackArgs *>(qb + o_jobs);
+    QueueItem *d_items = reinterpret_cast<QueueItem *>(qb + o_items);
+    unsigned *heads = reinterpret_cast<unsigned *>(qb + o_heads);
+
+    HIP_TRY(launch_prep_many(reinterpret_cast<const PrepArgs *>(qb + o_prep), (int)preps.size(), max_prep, st));
+    HIP_TRY(launch_init_many(reinterpret_cast<const InitArgs *>(qb + o_init), (int)inits.size(), max_total, st));
+    auto run_pass = [&](bool fp32) -> hc_status {
+        const TrackArgs *pj = d_jobs + (fp32 ? 0 : n_jobs);
+        HIP_TRY(launch_fill_u32(heads, 0u, 4, st));
+        for (int qi = 0; qi < 4; qi++) {
+            const int cnt = q_off[qi + 1] - q_off[qi];
+            if (cnt == 0) continue;
+            const bool param = (qi & 1) != 0;
+            if (qi < 2)
+                HIP_TRY(launch_track_queue(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
+                                           queue_waves(fp32, param), st));
+            else
+                HIP_TRY(launch_track_queue_terms(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
+                                                 queue_waves_terms(fp32, param), st));
+        }
         return HC_OK;
     };
-    for (int k = 0; k < n_jobs; k++) {
-        rc = refine_job(k);
-        if (rc != HC_OK) return rc;
-    }
-    if (mixed && o.crossing_check) {
-        // crossing check per job, then one FP64 pass over the queues and the
-        // refinement of the re-tracked paths
-        for (int k = 0; k < n_jobs; k++) {
-            const Plan &p = plan[k];
-            if (p.total == 0) continue;
-            DedupArgs da;
-            da.n = p.n;
-            da.n_start = p.j->n_start;
-            da.n_inst = p.j->n_inst;
-            da.total = p.total;
-            da.tol = kCrossTol;
-            da.endpoints = reinterpret_cast<const double *>(p.j->endpoints);
-            da.status = p.j->status;
-            da.s = c->h_jobs[(size_t)n_jobs + k].s;
-            HIP_TRY(launch_dedup(da, st));
-            InitArgs ir = p.init;
-            ir.retrack = 1;
-            HIP_TRY(launch_init(ir, st));
+    auto refine_all = [&]() -> hc_status {
+        for (int rk = 1; rk < kMaxN + 2; rk++) {
+            if (refs[rk].empty()) continue;
+            const RefineArgs *d = reinterpret_cast<const RefineArgs *>(qb + o_ref[rk]);
+            if (rk == kMaxN + 1)
+                HIP_TRY(launch_refine_terms_many(d, (int)refs[rk].size(), ref_items[rk], st));
+            else
+                HIP_TRY(launch_refine_many(rk, d, (int)refs[rk].size(), ref_items[rk], st));
         }
+        return HC_OK;
+    };
+    rc = run_pass(mixed);
+    if (rc != HC_OK) return rc;
+    if (mixed && !kInlineEsc) {
         rc = run_pass(false);
         if (rc != HC_OK) return rc;
-        for (int k = 0; k < n_jobs; k++) {
-            rc = refine_job(k);
-            if (rc != HC_OK) return rc;
-        }
+    }
+    rc = refine_all();
+    if (rc != HC_OK) return rc;
+    if (mixed && o.crossing_check) {
+        // crossing check of every job, one FP64 pass over the queues, then the
+        // refinement of the re-tracked paths
+        HIP_TRY(launch_dedup_many(reinterpret_cast<const DedupArgs *>(qb + o_dedup), (int)dedups.size(), max_inst,
+                                  st));
+        HIP_TRY(launch_init_many(reinterpret_cast<const InitArgs *>(qb + o_retr), (int)retracks.size(), max_total,
+                                 st));
+        rc = run_pass(false);
+        if (rc != HC_OK) return rc;
+        rc = refine_all();
+        if (rc != HC_OK) return rc;
     }
     return HC_OK;
 }

@@ -86,6 +86,7 @@ struct hc_ctx {
     hcx::DevBuf queue;   // batch: per-pass job descriptors, work items, queue heads
     std::vector<hcx::TrackArgs> h_jobs;   // host copies kept alive across the async uploads
     std::vector<hcx::QueueItem> h_items;
+    std::vector<unsigned char> h_blob;   // batch: staging of the one upload per call
     // hipGraph of the last hc_track_device call with use_graph, and its arguments
     bool graph_valid = false;
     std::vector<unsigned char> graph_key;

@@ -160,7 +160,13 @@ hipError_t launch_track_queue_terms(bool fp32, bool param, const TrackArgs *jobs
                                     int n_items, unsigned *head, int n_waves, hipStream_t st);
 int queue_waves_terms(bool fp32, bool param);
 hipError_t launch_refine_terms(const RefineArgs &a, hipStream_t st);
+hipError_t launch_refine_terms_many(const RefineArgs *a, int count, long long max_total, hipStream_t st);
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
+// Batch API: one launch per step over many jobs (argument arrays in device memory).
+hipError_t launch_prep_many(const PrepArgs *a, int count, long long max_work, hipStream_t st);
+hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, hipStream_t st);
+hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, hipStream_t st);
+hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, hipStream_t st);
 
 }  // namespace hcx

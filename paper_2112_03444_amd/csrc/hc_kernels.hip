@@ -382,9 +382,8 @@ __global__ __launch_bounds__(256) void k_track(const TrackArgs a)
 
 // ---------------------------------------------------------------- init (a1)
 
-__global__ void k_init(const InitArgs a)
+__device__ __forceinline__ void init_body(const InitArgs &a, long long g)
 {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.total) return;
     const long long b = g % a.n_start;
     const TrackState S = a.s;
@@ -420,16 +419,24 @@ __global__ void k_init(const InitArgs a)
     S.status[g] = kRunning;
 }
 
+__global__ void k_init(const InitArgs a) { init_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x); }
+
+// One launch for many jobs (batch API): job blockIdx.y, its blocks along x.
+__global__ void k_init_many(const InitArgs *a)
+{
+    init_body(a[blockIdx.y], (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------- crossing check
 
 // One block per instance.  Two paths of one instance that end on the same root
 // have crossed (one jumped onto the other's path); both start over in FP64.
 // A complex projection of every SUCCESS endpoint is kept in LDS and compared
 // first; candidates are then compared in full.
-__global__ __launch_bounds__(256) void k_dedup(const DedupArgs a)
+__device__ __forceinline__ void dedup_body(const DedupArgs &a, int inst)
 {
     __shared__ cx<double> proj[kDedupMax];
-    const int inst = blockIdx.x;
+    if (inst >= a.n_inst) return;
     const long long g0 = (long long)inst * a.n_start;
     const TrackState S = a.s;
     const bool check = a.n_start <= kDedupMax;
@@ -470,6 +477,10 @@ __global__ __launch_bounds__(256) void k_dedup(const DedupArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_dedup(const DedupArgs a) { dedup_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_dedup_many(const DedupArgs *a) { dedup_body(a[blockIdx.y], blockIdx.x); }
+
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st)
 {
     if (a.total == 0 || a.n_inst == 0) return hipSuccess;
@@ -481,9 +492,8 @@ hipError_t launch_dedup(const DedupArgs &a, hipStream_t st)
 
 // One thread per (instance, kernel-table slot): the slot's coefficient is the sum
 // over the terms mapped to it of mult * c_k(p), c_k(p) = const_k + sum val * p.
-__global__ void k_prep(const PrepArgs a)
+__device__ __forceinline__ void prep_body(const PrepArgs &a, long long gid)
 {
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (long long)a.n_inst * a.n_slots) return;
     const int inst = (int)(gid / a.n_slots);
     const int s = (int)(gid % a.n_slots);
@@ -518,6 +528,13 @@ __global__ void k_prep(const PrepArgs a)
         a.out32[2 * gid] = (float)re;
         a.out32[2 * gid + 1] = (float)im;
     }
+}
+
+__global__ void k_prep(const PrepArgs a) { prep_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x); }
+
+__global__ void k_prep_many(const PrepArgs *a)
+{
+    prep_body(a[blockIdx.y], (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------- refine (a8)
@@ -558,14 +575,15 @@ __device__ double residual_dense(tbl_ptr<double> cf, const cx<double> (&x)[N])
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void k_refine(const RefineArgs a)
+__device__ __forceinline__ void refine_body(const RefineArgs &a, int block)
 {
     // one wavefront per (instance, 64 consecutive paths): the instance, and so the
     // table address, is wavefront-uniform and the tables come in by scalar loads
     constexpr int T = dense_terms(N);
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
+    const int item = __builtin_amdgcn_readfirstlane(block * (blockDim.x >> 6) + wib);
+    if (a.total == 0) return;
     const int per_inst = (a.n_start + 63) / 64;
     const int inst = item / per_inst;
     const int b = (item - inst * per_inst) * 64 + lane;
@@ -651,6 +669,12 @@ __global__ __launch_bounds__(256) void k_refine(const RefineArgs a)
     }
 }
 
+template <int N>
+__global__ __launch_bounds__(256) void k_refine(const RefineArgs a) { refine_body<N>(a, blockIdx.x); }
+
+template <int N>
+__global__ __launch_bounds__(256) void k_refine_many(const RefineArgs *a) { refine_body<N>(a[blockIdx.y], blockIdx.x); }
+
 // ---------------------------------------------------------------- launchers
 
 __global__ void k_fill_u32(unsigned *p, unsigned value, int count)
@@ -717,6 +741,52 @@ static hipError_t launch_refine_n(const RefineArgs &a, hipStream_t st)
     const long long items = n_inst * ((a.n_start + 63) / 64);
     hipLaunchKernelGGL(k_refine<N>, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
+}
+
+// Many jobs: blocks = the largest job's block count along x, one job per y.
+hipError_t launch_prep_many(const PrepArgs *a, int count, long long max_work, hipStream_t st)
+{
+    if (count == 0 || max_work == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep_many, dim3((unsigned)((max_work + 255) / 256), (unsigned)count), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, hipStream_t st)
+{
+    if (count == 0 || max_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_many, dim3((unsigned)((max_total + 255) / 256), (unsigned)count), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, hipStream_t st)
+{
+    if (count == 0 || max_inst == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dedup_many, dim3((unsigned)max_inst, (unsigned)count), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_refine_many_n(const RefineArgs *a, int count, long long max_items, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_refine_many<N>, dim3((unsigned)((max_items + 3) / 4), (unsigned)count), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// max_items: the largest n_inst * ceil(n_start / 64) of the jobs
+hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, hipStream_t st)
+{
+    if (count == 0 || max_items == 0) return hipSuccess;
+    switch (n) {
+    case 1: return launch_refine_many_n<1>(a, count, max_items, st);
+    case 2: return launch_refine_many_n<2>(a, count, max_items, st);
+    case 3: return launch_refine_many_n<3>(a, count, max_items, st);
+    case 4: return launch_refine_many_n<4>(a, count, max_items, st);
+    case 5: return launch_refine_many_n<5>(a, count, max_items, st);
+    case 6: return launch_refine_many_n<6>(a, count, max_items, st);
+    case 7: return launch_refine_many_n<7>(a, count, max_items, st);
+    case 8: return launch_refine_many_n<8>(a, count, max_items, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st)

@@ -8,6 +8,7 @@
 // batch overlaps the ones in flight.  A batch is one hc_track_batch_device call
 // (persistent work-queue tracker); every path's arithmetic is independent of
 // what else is in the batch, so a request's results do not depend on the mix.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -176,6 +177,8 @@ hc_status launch_batch(hc_server *sv, Slot &sl)
     return HC_OK;
 }
 
+int request_class(const Request *r) { return 2 * r->sys->layout + (r->sys->kind == HC_PARAMETER ? 1 : 0); }
+
 void dispatch_loop(hc_server *sv)
 {
     (void)hipSetDevice(sv->ctx->device);
@@ -199,12 +202,21 @@ void dispatch_loop(hc_server *sv)
             return sv->bytes_inflight == 0 || sv->bytes_inflight + r->bytes <= (size_t)sv->o.hbm_budget;
         });
         if (sv->pending.empty() && sv->stop) break;
-        while (!sv->pending.empty() && (int)batch.size() < sv->o.max_batch_requests) {
-            Request *r = sv->pending.front();
+        // one batch holds requests of one class (table layout x homotopy kind), so
+        // it runs one tracking kernel and batches of different classes overlap on
+        // the device; within the class requests go in arrival order
+        const int cls = request_class(sv->pending.front());
+        for (auto it = sv->pending.begin();
+             it != sv->pending.end() && (int)batch.size() < sv->o.max_batch_requests;) {
+            Request *r = *it;
+            if (request_class(r) != cls) {
+                ++it;
+                continue;
+            }
             if (!batch.empty() && sv->bytes_inflight + bytes + r->bytes > (size_t)sv->o.hbm_budget) break;
             batch.push_back(r);
             bytes += r->bytes;
-            sv->pending.pop_front();
+            it = sv->pending.erase(it);
         }
         Slot &sl = *free_slot;
         sl.busy = true;
@@ -235,13 +247,36 @@ void complete_loop(hc_server *sv)
             return true;
         });
         if (sv->inflight.empty()) break;
-        Slot *sl = sv->inflight.front();
+        // the batch the device finished first (batches of different classes take
+        // different times, so completion is not in dispatch order)
+        Slot *sl = nullptr;
+        std::vector<Slot *> cand(sv->inflight.begin(), sv->inflight.end());
         lk.unlock();
+        for (;;) {
+            for (Slot *c : cand) {
+                if (c->rc != HC_OK) {
+                    sl = c;
+                    break;
+                }
+                const hipError_t e = hipEventQuery(c->done);
+                if (e == hipSuccess) {
+                    sl = c;
+                    break;
+                }
+                if (e != hipErrorNotReady) {
+                    c->rc = fail(HC_E_DEVICE, "server: %s", hipGetErrorString(e));
+                    sl = c;
+                    break;
+                }
+            }
+            if (sl) break;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+            cand.assign(sv->inflight.begin(), sv->inflight.end());
+            lk.unlock();
+        }
         const auto t0 = clk::now();
-        if (sl->rc == HC_OK) {
-            const hipError_t e = hipEventSynchronize(sl->done);
-            if (e != hipSuccess) sl->rc = fail(HC_E_DEVICE, "server: %s", hipGetErrorString(e));
-        } else {
+        if (sl->rc != HC_OK) {
             // whatever the failed launch left on the stream finishes before reuse
             (void)hipStreamSynchronize(sl->ctx->own_stream);
         }
@@ -272,7 +307,7 @@ void complete_loop(hc_server *sv)
         sl->reqs.clear();
         sv->bytes_inflight -= sl->bytes;
         sl->busy = false;
-        sv->inflight.pop_front();
+        sv->inflight.erase(std::find(sv->inflight.begin(), sv->inflight.end(), sl));
         sv->cv_done.notify_all();
         sv->cv_dispatch.notify_all();
     }

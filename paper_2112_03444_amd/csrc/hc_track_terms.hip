@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256, 2) void k_track_queue_terms(const TrackArgs *_
 // layout: Newton on F(x; c1) at t = 1 with the group solver, then the relative
 // backward error eta = max_i |F_i| / sum_k |c_ik| |m_k(x)|.  One path per group
 // of 16 lanes, 4 paths per wavefront.
-__global__ __launch_bounds__(256) void k_refine_terms(const RefineArgs a)
+__device__ __forceinline__ void refine_terms_body(const RefineArgs &a, int block)
 {
     constexpr int NM = kTermsN, G = 16;
     const int lane = threadIdx.x & 63;
@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_refine_terms(const RefineArgs a)
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ __align__(16) unsigned char buf[4 * kTermsLdsCx * sizeof(cx<double>)];
     void *lds = buf + (size_t)wib * kTermsLdsCx * sizeof(cx<double>);
-    const long long gid = ((long long)blockIdx.x * 4 + wib) * 4 + (lane >> 4);
+    if (a.total == 0) return;
+    const long long gid = ((long long)block * 4 + wib) * 4 + (lane >> 4);
     const bool valid = gid < a.total;
     const long long g = valid ? gid : 0;  // spare groups redo path 0 and write nothing
     const int n = a.n, T = a.n_tslots;
@@ -186,6 +187,13 @@ __global__ __launch_bounds__(256) void k_refine_terms(const RefineArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_refine_terms(const RefineArgs a) { refine_terms_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_refine_terms_many(const RefineArgs *a)
+{
+    refine_terms_body(a[blockIdx.y], blockIdx.x);
+}
+
 namespace {
 
 template <typename K>
@@ -243,6 +251,15 @@ int queue_waves_terms(bool fp32, bool param)
                            : resident_waves_terms(k_track_queue_terms<double, true>);
     return fp32 ? resident_waves_terms(k_track_queue_terms<float, false>)
                 : resident_waves_terms(k_track_queue_terms<double, false>);
+}
+
+// max_total: the largest job's path count
+hipError_t launch_refine_terms_many(const RefineArgs *a, int count, long long max_total, hipStream_t st)
+{
+    if (count == 0 || max_total == 0) return hipSuccess;
+    const long long waves = (max_total + 3) / 4;
+    hipLaunchKernelGGL(k_refine_terms_many, dim3((unsigned)((waves + 3) / 4), (unsigned)count), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_refine_terms(const RefineArgs &a, hipStream_t st)
