@@ -90,6 +90,13 @@ __device__ __forceinline__ cx<R> ldl(lds_tab<R> p, int i)
     return {p[i].re, p[i].im};
 }
 
+template <typename R>
+__device__ __forceinline__ void stl(lds_tab<R> p, int i, cx<R> v)
+{
+    p[i].re = v.re;
+    p[i].im = v.im;
+}
+
 // Coefficient q of the lane's equation, from an LDS slot (coefficient-major,
 // stride n; p already offset by the equation) ...
 template <int N, typename R>
@@ -343,12 +350,20 @@ __device__ __forceinline__ bool group_any(bool p, int base)
 // with partial pivoting across the group.  Lane r receives component r of the
 // solution in dxr (0 in padding lanes) and every lane the squared 2-norm of the
 // whole solution in nd (summed in the same order everywhere, so identical in the
-// group).  Must run with the whole wavefront active.  Returns true if a pivot is
-// (numerically) zero.
+// group).  Must run with the whole wavefront active, in a block of 4
+// wavefronts.  Returns true if a pivot is (numerically) zero.
+//
+// The pivot row's remaining entries reach the group through LDS: the pivot lane
+// stores them in the group's slot and every lane of the group reads them back
+// (one address per group: broadcast reads), about a quarter of the LDS
+// instructions of one ds_bpermute per dword.
 template <int N, int G, typename R>
 __device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base, cx<R> &dxr, R &nd)
 {
     constexpr unsigned GM = G - 1;
+    __shared__ cx<R> pivbuf[4 * (64 / G) * (N + 1)];
+    const lds_tab<R> piv =
+        (lds_tab<R>)(pivbuf + ((int)(threadIdx.x >> 6) * (64 / G) + base / G) * (N + 1));
     int pos = r < N ? -1 : 4 * G;  // position at which this row became pivotal
     int pl[N];                     // group-relative lane of the pivot of each position
     cx<R> inv_own = {R(0), R(0)};
@@ -361,9 +376,16 @@ __device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base
         const int p = (int)(GM - (kmax & GM));
         sing |= ((kmax & 0x7fffffffu & ~GM) == 0u);
         pl[k] = p;
+        if (r == p) {
+#pragma unroll
+            for (int c = k; c <= N; c++) stl(piv, c, row[c]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         cx<R> P[N + 1];
 #pragma unroll
-        for (int c = k; c <= N; c++) P[c] = bcast(row[c], base + p);
+        for (int c = k; c <= N; c++) P[c] = ldl(piv, c);
         const cx<R> inv = crecip(P[k]);
         const bool piv = (r == p);
         pos = piv ? k : pos;
@@ -551,12 +573,6 @@ constexpr int kTermsN = 16;
 // component per lane) and each lane's row accumulator, room for FP64.
 constexpr int kTermsLdsCx = 64 + 64 * (kTermsN + 1);
 
-template <typename R>
-__device__ __forceinline__ void stl(lds_tab<R> p, int i, cx<R> v)
-{
-    p[i].re = v.re;
-    p[i].im = v.im;
-}
 
 // Row r of [H_x | rhs] from the lane's term list (vars, c1 and, for a parameter
 // homotopy, c0: the equation's T slots), at the point held in xg (component j
