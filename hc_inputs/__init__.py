@@ -28,6 +28,9 @@ __all__ = [
     "complex_gaussian",
     "dense_quadratic_instances",
     "unit_gammas",
+    "monomials_upto",
+    "support_system",
+    "support_instances",
     "WORKLOADS",
     "workload",
 ]
@@ -76,6 +79,46 @@ def dense_quadratic_system(n: int) -> PolySystem:
     term_eq = np.repeat(np.arange(n, dtype=np.int32), T)
     term_exp = np.tile(mons, (n, 1)).astype(np.int32)
     return PolySystem(n=n, term_eq=term_eq, term_exp=term_exp)
+
+
+def monomials_upto(n: int, deg: int, vars_) -> np.ndarray:
+    """Exponent vectors (length n) of every monomial of degree <= deg in the
+    unknowns listed in vars_, [m, n] int32, in graded lexicographic order."""
+    vars_ = list(vars_)
+    rows = []
+
+    def rec(i, left, e):
+        if i == len(vars_):
+            rows.append(e.copy())
+            return
+        for a in range(left + 1):
+            e[vars_[i]] = a
+            rec(i + 1, left - a, e)
+        e[vars_[i]] = 0
+
+    rec(0, deg, np.zeros(n, np.int32))
+    rows.sort(key=lambda r: (int(r.sum()), tuple(-r)))
+    return np.stack(rows).astype(np.int32)
+
+
+def support_system(n: int, spec) -> PolySystem:
+    """Equation i holds every monomial of degree <= d_i in the unknowns V_i, for
+    spec = [(d_1, V_1), ..., (d_n, V_n)]: dense on its own support, of degree d_i."""
+    eqs, exps = [], []
+    for i, (d, vs) in enumerate(spec):
+        m = monomials_upto(n, d, vs)
+        eqs.append(np.full(len(m), i, np.int32))
+        exps.append(m)
+    return PolySystem(n=n, term_eq=np.concatenate(eqs), term_exp=np.concatenate(exps).astype(np.int32))
+
+
+def support_instances(n: int, spec, n_inst: int, seed: int) -> Tuple[PolySystem, np.ndarray, np.ndarray]:
+    """support_system with CN(0, 1) coefficients and unit gammas."""
+    sys_ = support_system(n, spec)
+    rng = np.random.default_rng(seed)
+    coef = complex_gaussian(rng, (n_inst, sys_.n_terms))
+    gam = unit_gammas(rng, n_inst)
+    return sys_, np.ascontiguousarray(coef), np.ascontiguousarray(gam)
 
 
 def complex_gaussian(rng: np.random.Generator, shape) -> np.ndarray:

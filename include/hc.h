@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define HC_MAX_N 16 /* largest number of unknowns the GPU path handles */
+#define HC_MAX_N 20 /* largest number of unknowns the GPU path handles */
 
 typedef struct {
     double re, im;

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhc.so")
 SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp"),
            os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip"),
-           os.path.join(CSRC, "hc_track_terms.hip")]
+           os.path.join(CSRC, "hc_terms_q16.hip"), os.path.join(CSRC, "hc_terms_g16.hip"),
+           os.path.join(CSRC, "hc_terms_g20.hip")]
 ARCH = "gfx950"
 
 

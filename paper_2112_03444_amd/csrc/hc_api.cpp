@@ -117,6 +117,8 @@ static void free_system_tables(hc_system *s)
     (void)hipFree(s->d_map_col);
     (void)hipFree(s->d_map_val);
     (void)hipFree(s->d_vars);
+    (void)hipFree(s->d_sdeg);
+    (void)hipFree(s->d_eqdeg);
 }
 
 void hc_destroy(hc_ctx *c)
@@ -151,19 +153,42 @@ hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layo
     if (!c || !d || !out) return fail(HC_E_INVALID, "hc_load_system: NULL argument");
     if (d->n < 1) return fail(HC_E_INVALID, "hc_load_system: n = %d", d->n);
     if (d->n > HC_MAX_N) return fail(HC_E_UNSUPPORTED, "hc_load_system: n = %d > %d", d->n, HC_MAX_N);
-    if (layout == HC_LAYOUT_AUTO) layout = d->n <= 8 ? HC_LAYOUT_DENSE : HC_LAYOUT_TERMS;
-    if (layout != HC_LAYOUT_DENSE && layout != HC_LAYOUT_TERMS)
-        return fail(HC_E_UNSUPPORTED, "hc_load_system: layout %d", layout);
-    if (layout == HC_LAYOUT_DENSE && d->n > 8)
-        return fail(HC_E_UNSUPPORTED, "hc_load_system: dense tables need n <= 8 (n = %d)", d->n);
-    if (layout == HC_LAYOUT_TERMS && d->n < 2)
-        return fail(HC_E_UNSUPPORTED, "hc_load_system: term lists need n >= 2");
     if (d->n_terms < 1 || !d->term_eq || !d->term_exp)
         return fail(HC_E_INVALID, "hc_load_system: empty or missing term tables");
     if (d->kind != HC_TOTAL_DEGREE && d->kind != HC_PARAMETER)
         return fail(HC_E_INVALID, "hc_load_system: kind = %d", d->kind);
     if (d->n_params < 0) return fail(HC_E_INVALID, "hc_load_system: n_params = %d", d->n_params);
     const int n = d->n, nt = d->n_terms;
+    // degrees of the terms (validated before the layout is chosen)
+    std::vector<int> tdeg(nt, 0);
+    int max_deg = 0;
+    for (int k = 0; k < nt; k++) {
+        if (d->term_eq[k] < 0 || d->term_eq[k] >= n)
+            return fail(HC_E_INVALID, "hc_load_system: term_eq[%d] = %d out of range", k, d->term_eq[k]);
+        for (int j = 0; j < n; j++) {
+            const int e = d->term_exp[(size_t)k * n + j];
+            if (e < 0) return fail(HC_E_INVALID, "hc_load_system: negative exponent in term %d", k);
+            if (e > kMaxTermDeg)
+                return fail(HC_E_UNSUPPORTED, "hc_load_system: term %d has degree > %d", k, kMaxTermDeg);
+            tdeg[k] += e;
+        }
+        if (tdeg[k] > kMaxTermDeg)
+            return fail(HC_E_UNSUPPORTED, "hc_load_system: term %d has degree %d > %d", k, tdeg[k], kMaxTermDeg);
+        max_deg = std::max(max_deg, tdeg[k]);
+    }
+    if (layout == HC_LAYOUT_AUTO) layout = (n <= 8 && max_deg <= 2) ? HC_LAYOUT_DENSE : HC_LAYOUT_TERMS;
+    if (layout != HC_LAYOUT_DENSE && layout != HC_LAYOUT_TERMS)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: layout %d", layout);
+    if (layout == HC_LAYOUT_DENSE && n > 8)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: dense tables need n <= 8 (n = %d)", n);
+    if (layout == HC_LAYOUT_DENSE && max_deg > 2)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: dense tables need degree <= 2 (a term has degree %d)",
+                    max_deg);
+    if (layout == HC_LAYOUT_TERMS && n < 2)
+        return fail(HC_E_UNSUPPORTED, "hc_load_system: term lists need n >= 2");
+    // term-list kernel kind: the quadratic kernels where they apply
+    const int tk = layout != HC_LAYOUT_TERMS ? 0 : (max_deg <= 2 && n <= 16) ? 0 : n <= 16 ? 1 : 2;
+    const bool gen = layout == HC_LAYOUT_TERMS && tk != 0;
     if (!d->coef_rowptr && d->n_params != nt)
         return fail(HC_E_INVALID, "hc_load_system: identity coefficient map needs n_params == n_terms (%d != %d)",
                     d->n_params, nt);
@@ -189,45 +214,53 @@ hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layo
     s->n_params = d->n_params;
     s->kind = d->kind;
     s->layout = layout;
+    s->tk = tk;
+    s->max_deg = max_deg;
     s->deg.assign(n, 0);
-    for (int k = 0; k < nt; k++) {
-        if (d->term_eq[k] < 0 || d->term_eq[k] >= n) {
-            delete s;
-            return fail(HC_E_INVALID, "hc_load_system: term_eq[%d] = %d out of range", k, d->term_eq[k]);
-        }
-    }
-    // term lists: slot j of equation i is the j-th term of equation i
+    for (int k = 0; k < nt; k++) s->deg[d->term_eq[k]] = std::max(s->deg[d->term_eq[k]], tdeg[k]);
+    // term lists: slot j of equation i is its j-th term; the general-degree kinds
+    // order each equation's terms by decreasing degree (stable)
     std::vector<int> eq_count(n, 0), term_pos(nt);
-    for (int k = 0; k < nt; k++) term_pos[k] = eq_count[d->term_eq[k]]++;
+    if (gen) {
+        std::vector<int> order(nt);
+        for (int k = 0; k < nt; k++) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tdeg[x] > tdeg[y]; });
+        for (int k : order) term_pos[k] = eq_count[d->term_eq[k]]++;
+    } else {
+        for (int k = 0; k < nt; k++) term_pos[k] = eq_count[d->term_eq[k]]++;
+    }
     s->T = layout == HC_LAYOUT_DENSE ? dense_terms(n) : *std::max_element(eq_count.begin(), eq_count.end());
 
     // a0: map every term to its slot in the kernel tables
     const int n_slots = n * s->T;
     std::vector<std::vector<std::pair<int, int>>> slot_terms(n_slots);
-    std::vector<unsigned short> vars(layout == HC_LAYOUT_TERMS ? n_slots : 0, 0xFFFFu);
+    std::vector<unsigned short> vars((layout == HC_LAYOUT_TERMS && !gen) ? n_slots : 0, 0xFFFFu);
+    std::vector<unsigned long long> vars64(gen ? n_slots : 0, ~0ull);
+    std::vector<int> sdeg(gen ? s->T : 0, 0);
     for (int k = 0; k < nt; k++) {
         const int i = d->term_eq[k];
-        int deg = 0, a = -1, b = -1;
-        for (int j = 0; j < n; j++) {
-            const int e = d->term_exp[(size_t)k * n + j];
-            if (e < 0) {
-                delete s;
-                return fail(HC_E_INVALID, "hc_load_system: negative exponent in term %d", k);
-            }
-            deg += e;
-            for (int r = 0; r < e && deg <= 2; r++) {
+        const int deg = tdeg[k];
+        if (gen) {
+            // factor bytes, variables in increasing order with repetition
+            const int q = i * s->T + term_pos[k];
+            unsigned long long v = ~0ull;
+            int f = 0;
+            for (int j = 0; j < n; j++)
+                for (int e = 0; e < d->term_exp[(size_t)k * n + j]; e++, f++)
+                    v = (v & ~(0xFFull << (8 * f))) | ((unsigned long long)j << (8 * f));
+            vars64[q] = v;
+            sdeg[term_pos[k]] = std::max(sdeg[term_pos[k]], deg);
+            slot_terms[q].push_back({k, 1});
+            continue;
+        }
+        int a = -1, b = -1;
+        for (int j = 0; j < n; j++)
+            for (int e = 0; e < d->term_exp[(size_t)k * n + j]; e++) {
                 if (a < 0) a = j;
                 else b = j;
             }
-        }
-        if (deg > 2) {
-            delete s;
-            return fail(HC_E_UNSUPPORTED, "hc_load_system: term %d has degree %d > 2", k, deg);
-        }
-        s->deg[i] = std::max(s->deg[i], deg);
         if (layout == HC_LAYOUT_TERMS) {
-            // c x_a x_b with 0xFF for a missing factor (x_a^2: a = b)
-            if (deg == 2 && b < 0) b = a;
+            // c x_a x_b with 0xFF for a missing factor
             const int q = i * s->T + term_pos[k];
             vars[q] = (unsigned short)((a < 0 ? 0xFFu : (unsigned)a) | ((b < 0 ? 0xFFu : (unsigned)b) << 8));
             slot_terms[q].push_back({k, 1});
@@ -251,7 +284,7 @@ hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layo
             return fail(HC_E_UNSUPPORTED, "hc_load_system: equation %d has degree 0", i);
         }
         if (s->deg[i] == 2) s->deg2 |= 1u << i;
-        bez *= s->deg[i];
+        bez = bez > (int64_t)(INT64_MAX / s->deg[i]) ? INT64_MAX : bez * s->deg[i];
     }
     s->bezout = bez;
     std::vector<int> slot_ptr(n_slots + 1, 0), slot_term, slot_mult;
@@ -267,7 +300,18 @@ hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layo
     if (e == hipSuccess) e = upload(&s->d_slot_ptr, slot_ptr.data(), slot_ptr.size());
     if (e == hipSuccess) e = upload(&s->d_slot_term, slot_term.data(), slot_term.size());
     if (e == hipSuccess) e = upload(&s->d_slot_mult, slot_mult.data(), slot_mult.size());
-    if (e == hipSuccess && !vars.empty()) e = upload(&s->d_vars, vars.data(), vars.size());
+    if (e == hipSuccess && !vars.empty()) {
+        unsigned short *dv = nullptr;
+        e = upload(&dv, vars.data(), vars.size());
+        s->d_vars = dv;
+    }
+    if (e == hipSuccess && !vars64.empty()) {
+        unsigned long long *dv = nullptr;
+        e = upload(&dv, vars64.data(), vars64.size());
+        s->d_vars = dv;
+        if (e == hipSuccess) e = upload(&s->d_sdeg, sdeg.data(), sdeg.size());
+        if (e == hipSuccess) e = upload(&s->d_eqdeg, s->deg.data(), s->deg.size());
+    }
     if (e == hipSuccess && d->coef_const) {
         s->has_const = true;
         e = upload(&s->d_term_const, reinterpret_cast<const double *>(d->coef_const), (size_t)nt * 2);
@@ -356,12 +400,21 @@ static hc_status check_opts(const hc_opts &o)
     return HC_OK;
 }
 
+// Batch path: one device queue per [dense | term-list kind] x [total degree |
+// parameter], and one refinement launch per dense n and per term-list kind.
+constexpr int kQueues = 2 + 2 * kTermKindCount;
+constexpr int kRefSlots = kMaxN + 1 + kTermKindCount;
+
 // Lanes per path: one row of [H_x | rhs] per lane (dense tables: G = 4 for
-// n <= 4, 8 for n <= 8; term lists: always 16) unless one path per lane is asked
-// for (dense tables) or n = 1.  -1: the option does not fit the system.
+// n <= 4, 8 for n <= 8; term lists: 16, or 32 for n > 16) unless one path per
+// lane is asked for (dense tables) or n = 1.  -1: the option does not fit the
+// system.
 static int choose_lanes_per_path(const hc_opts &o, const hc_system *s)
 {
-    if (s->layout == HC_LAYOUT_TERMS) return (o.lanes_per_path == 0 || o.lanes_per_path == 16) ? 16 : -1;
+    if (s->layout == HC_LAYOUT_TERMS) {
+        const int g = term_kind_lanes(s->tk);
+        return (o.lanes_per_path == 0 || o.lanes_per_path == g) ? g : -1;
+    }
     if (s->n < 2) return 1;
     if (o.lanes_per_path == 1) return 1;
     const int g = group_lanes(s->n);
@@ -370,7 +423,15 @@ static int choose_lanes_per_path(const hc_opts &o, const hc_system *s)
     return g;
 }
 
-static int lanes_for(const hc_system *s) { return s->layout == HC_LAYOUT_TERMS ? 16 : group_lanes(s->n); }
+static int lanes_for(const hc_system *s)
+{
+    return s->layout == HC_LAYOUT_TERMS ? term_kind_lanes(s->tk) : group_lanes(s->n);
+}
+
+// Term lists of the general-degree kinds carry their equations' degrees (start
+// system and start points of any degree).
+static const int *eqdeg_of(const hc_system *s) { return s->layout == HC_LAYOUT_TERMS ? s->d_eqdeg : nullptr; }
+static const int *sdeg_of(const hc_system *s) { return s->layout == HC_LAYOUT_TERMS ? s->d_sdeg : nullptr; }
 
 // Paths per work item.  Group layouts pop items from a device counter, so small
 // items balance the wavefronts (measured best: 2 paths per lane group); the
@@ -509,6 +570,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ia.n_start = n_start;
     ia.total = total;
     ia.deg2 = s->deg2;
+    ia.eqdeg = eqdeg_of(s);
     ia.start = reinterpret_cast<const double *>(start);
     ia.h0 = o.h0;
     ia.s = S;
@@ -548,6 +610,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ta.head = reinterpret_cast<unsigned *>(static_cast<char *>(c->counter.p) + 32);
     ta.vars = s->d_vars;
     ta.n_tslots = s->T;
+    ta.sdeg = sdeg_of(s);
+    ta.eqdeg = eqdeg_of(s);
     const int wpb = 4;
 
     // one pass = launches until no path is left suspended by steps_per_launch
@@ -570,7 +634,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
                 HIP_TRY(launch_track(n, fp32, ta, wpb, st));
             } else {
                 HIP_TRY(launch_fill_u32(ta.head, 0u, 1, st));
-                if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_track_terms(fp32, ta, st));
+                if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_track_terms(s->tk, fp32, ta, st));
                 else HIP_TRY(launch_track_group(n, fp32, ta, st));
             }
             if (fp32) c->launches_fp32++;
@@ -621,7 +685,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ra.n = n;
     ra.n_tslots = s->T;
     ra.vars = s->d_vars;
-    if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
+    ra.sdeg = sdeg_of(s);
+    if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(s->tk, ra, st));
     else HIP_TRY(launch_refine(n, ra, st));
     if (prof) HIP_TRY(hipEventRecord(c->ev[5], st));
     if (mixed && o.crossing_check) {
@@ -641,7 +706,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         HIP_TRY(launch_init(ir, st));
         rc = run_pass(false, 1.0, 0);
         if (rc != HC_OK) return rc;
-        if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(ra, st));
+        if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(s->tk, ra, st));
         else HIP_TRY(launch_refine(n, ra, st));
     }
     if (prof) {
@@ -914,7 +979,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     std::vector<InitArgs> inits;
     long long max_prep = 0, max_total = 0;
     // queues: [dense | term lists] x [total degree | parameter]
-    std::vector<QueueItem> qs[4];
+    std::vector<QueueItem> qs[kQueues];
     std::vector<int> job_n(n_jobs);
     for (int k = 0; k < n_jobs; k++) {
         Plan &p = plan[k];
@@ -970,6 +1035,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ia.n_start = p.j->n_start;
         ia.total = p.total;
         ia.deg2 = p.s->deg2;
+        ia.eqdeg = eqdeg_of(p.s);
         ia.start = reinterpret_cast<const double *>(p.j->start);
         ia.h0 = o.h0;
         ia.s = S;
@@ -1017,8 +1083,10 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             ta.stage_count = c->profiling ? stage_ctr : nullptr;
             ta.vars = p.s->d_vars;
             ta.n_tslots = p.s->T;
+            ta.sdeg = sdeg_of(p.s);
+            ta.eqdeg = eqdeg_of(p.s);
         }
-        std::vector<QueueItem> &q = qs[(p.s->layout == HC_LAYOUT_TERMS ? 2 : 0) + (p.param ? 1 : 0)];
+        std::vector<QueueItem> &q = qs[(p.s->layout == HC_LAYOUT_TERMS ? 2 + 2 * p.s->tk : 0) + (p.param ? 1 : 0)];
         for (int i = 0; i < p.j->n_inst; i++)
             for (int tb = 0; tb < p.j->n_start; tb += p.tpi)
                 q.push_back({k, i, tb, std::min(tb + p.tpi, p.j->n_start)});
@@ -1026,18 +1094,18 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     // larger systems first: their items are the longest
     auto by_n = [&](const QueueItem &x, const QueueItem &y) { return job_n[x.job] > job_n[y.job]; };
     c->h_items.clear();
-    int q_off[5] = {0, 0, 0, 0, 0};
-    for (int qi = 0; qi < 4; qi++) {
+    int q_off[kQueues + 1] = {};
+    for (int qi = 0; qi < kQueues; qi++) {
         std::stable_sort(qs[qi].begin(), qs[qi].end(), by_n);
         c->h_items.insert(c->h_items.end(), qs[qi].begin(), qs[qi].end());
         q_off[qi + 1] = (int)c->h_items.size();
     }
     // refinement, crossing-check and re-tracking arguments per job; refinement
     // launches once per dense n and once for the term lists
-    std::vector<RefineArgs> refs[kMaxN + 2];  // [n] dense, [kMaxN + 1] term lists
+    std::vector<RefineArgs> refs[kRefSlots];  // [n] dense, [kMaxN + 1 + kind] term lists
     std::vector<DedupArgs> dedups;
     std::vector<InitArgs> retracks;
-    long long ref_items[kMaxN + 2] = {};
+    long long ref_items[kRefSlots] = {};
     int max_inst = 0;
     for (int k = 0; k < n_jobs; k++) {
         const Plan &p = plan[k];
@@ -1060,9 +1128,10 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ra.n = p.n;
         ra.n_tslots = p.s->T;
         ra.vars = p.s->d_vars;
-        const int rk = p.s->layout == HC_LAYOUT_TERMS ? kMaxN + 1 : p.n;
+        ra.sdeg = sdeg_of(p.s);
+        const int rk = p.s->layout == HC_LAYOUT_TERMS ? kMaxN + 1 + p.s->tk : p.n;
         refs[rk].push_back(ra);
-        ref_items[rk] = std::max(ref_items[rk], rk == kMaxN + 1 ? p.total
+        ref_items[rk] = std::max(ref_items[rk], rk > kMaxN ? p.total
                                                                 : (long long)p.j->n_inst * ((p.j->n_start + 63) / 64));
         DedupArgs da;
         da.n = p.n;
@@ -1093,9 +1162,9 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     const size_t o_init = place(inits.size() * sizeof(InitArgs));
     const size_t o_dedup = place(dedups.size() * sizeof(DedupArgs));
     const size_t o_retr = place(retracks.size() * sizeof(InitArgs));
-    size_t o_ref[kMaxN + 2];
-    for (int rk = 0; rk < kMaxN + 2; rk++) o_ref[rk] = place(refs[rk].size() * sizeof(RefineArgs));
-    const size_t o_heads = place(4 * sizeof(unsigned));
+    size_t o_ref[kRefSlots];
+    for (int rk = 0; rk < kRefSlots; rk++) o_ref[rk] = place(refs[rk].size() * sizeof(RefineArgs));
+    const size_t o_heads = place(kQueues * sizeof(unsigned));
     c->h_blob.assign(off, 0);
     auto put_arr = [&](size_t at, const void *src, size_t bytes) {
         if (bytes) std::memcpy(c->h_blob.data() + at, src, bytes);
@@ -1106,7 +1175,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     put_arr(o_init, inits.data(), inits.size() * sizeof(InitArgs));
     put_arr(o_dedup, dedups.data(), dedups.size() * sizeof(DedupArgs));
     put_arr(o_retr, retracks.data(), retracks.size() * sizeof(InitArgs));
-    for (int rk = 0; rk < kMaxN + 2; rk++) put_arr(o_ref[rk], refs[rk].data(), refs[rk].size() * sizeof(RefineArgs));
+    for (int rk = 0; rk < kRefSlots; rk++) put_arr(o_ref[rk], refs[rk].data(), refs[rk].size() * sizeof(RefineArgs));
     HIP_TRY(c->queue.ensure(off));
     char *qb = static_cast<char *>(c->queue.p);
     HIP_TRY(hipMemcpyAsync(qb, c->h_blob.data(), o_heads, hipMemcpyHostToDevice, st));
@@ -1118,8 +1187,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     HIP_TRY(launch_init_many(reinterpret_cast<const InitArgs *>(qb + o_init), (int)inits.size(), max_total, st));
     auto run_pass = [&](bool fp32) -> hc_status {
         const TrackArgs *pj = d_jobs + (fp32 ? 0 : n_jobs);
-        HIP_TRY(launch_fill_u32(heads, 0u, 4, st));
-        for (int qi = 0; qi < 4; qi++) {
+        HIP_TRY(launch_fill_u32(heads, 0u, kQueues, st));
+        for (int qi = 0; qi < kQueues; qi++) {
             const int cnt = q_off[qi + 1] - q_off[qi];
             if (cnt == 0) continue;
             const bool param = (qi & 1) != 0;
@@ -1127,17 +1196,17 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
                 HIP_TRY(launch_track_queue(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
                                            queue_waves(fp32, param), st));
             else
-                HIP_TRY(launch_track_queue_terms(fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
-                                                 queue_waves_terms(fp32, param), st));
+                HIP_TRY(launch_track_queue_terms((qi - 2) / 2, fp32, param, pj, d_items + q_off[qi], cnt, heads + qi,
+                                                 queue_waves_terms((qi - 2) / 2, fp32, param), st));
         }
         return HC_OK;
     };
     auto refine_all = [&]() -> hc_status {
-        for (int rk = 1; rk < kMaxN + 2; rk++) {
+        for (int rk = 1; rk < kRefSlots; rk++) {
             if (refs[rk].empty()) continue;
             const RefineArgs *d = reinterpret_cast<const RefineArgs *>(qb + o_ref[rk]);
-            if (rk == kMaxN + 1)
-                HIP_TRY(launch_refine_terms_many(d, (int)refs[rk].size(), ref_items[rk], st));
+            if (rk > kMaxN)
+                HIP_TRY(launch_refine_terms_many(rk - kMaxN - 1, d, (int)refs[rk].size(), ref_items[rk], st));
             else
                 HIP_TRY(launch_refine_many(rk, d, (int)refs[rk].size(), ref_items[rk], st));
         }

@@ -41,6 +41,11 @@ namespace {
 
 __device__ __forceinline__ unsigned umax(unsigned a, unsigned b) { return a > b ? a : b; }
 
+// ds_swizzle bit-mode pattern that exchanges lanes i and i ^ 16 inside each
+// 32-lane half (and-mask 0x1F, or-mask 0, xor-mask 0x10): the step of the group
+// reductions that crosses the two rows of a 32-lane group.
+constexpr int kSwzXor16 = 0x1F | (0x10 << 10);
+
 template <int G>
 __device__ __forceinline__ unsigned group_max(unsigned v)
 {
@@ -50,6 +55,7 @@ __device__ __forceinline__ unsigned group_max(unsigned v)
     v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
     if (G >= 8) v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
     if (G >= 16) v = umax(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    if (G >= 32) v = umax(v, (unsigned)__builtin_amdgcn_ds_swizzle((int)v, kSwzXor16));
     return v;
 }
 
@@ -325,6 +331,14 @@ __device__ __forceinline__ double dpp(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+__device__ __forceinline__ double swz_xor16(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), kSwzXor16);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), kSwzXor16);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over the G lanes of a group by butterflies (xor 1, xor 2, then the half-row
 // and row mirrors).  Each step adds the same two operands on both sides of a
 // pair, so every lane of the group ends with the identical sum.  The whole group
@@ -336,6 +350,7 @@ __device__ __forceinline__ double group_sum(double v)
     v = v + dpp<0x4E>(v);
     if (G >= 8) v = v + dpp<0x141>(v);
     if (G >= 16) v = v + dpp<0x140>(v);
+    if (G >= 32) v = v + swz_xor16(v);
     return v;
 }
 
@@ -353,58 +368,68 @@ __device__ __forceinline__ bool group_any(bool p, int base)
 // group).  Must run with the whole wavefront active, in a block of 4
 // wavefronts.  Returns true if a pivot is (numerically) zero.
 //
+// nrt <= N is the system's size, the same in every group of the wavefront:
+// rows r >= nrt never become pivotal and the elimination stops after nrt
+// positions.  Entries of rows r < nrt in columns nrt..N-1 must be zero, so the
+// result is that of the nrt x nrt system.
+//
 // The pivot row's remaining entries reach the group through LDS: the pivot lane
 // stores them in the group's slot and every lane of the group reads them back
 // (one address per group: broadcast reads), about a quarter of the LDS
 // instructions of one ds_bpermute per dword.
 template <int N, int G, typename R>
-__device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base, cx<R> &dxr, R &nd)
+__device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base, cx<R> &dxr, R &nd, int nrt = N)
 {
     constexpr unsigned GM = G - 1;
     __shared__ cx<R> pivbuf[4 * (64 / G) * (N + 1)];
     const lds_tab<R> piv =
         (lds_tab<R>)(pivbuf + ((int)(threadIdx.x >> 6) * (64 / G) + base / G) * (N + 1));
-    int pos = r < N ? -1 : 4 * G;  // position at which this row became pivotal
-    int pl[N];                     // group-relative lane of the pivot of each position
+    int pos = r < nrt ? -1 : 4 * G;  // position at which this row became pivotal
+    int pl[N];                       // group-relative lane of the pivot of each position
     cx<R> inv_own = {R(0), R(0)};
     bool sing = false;
 #pragma unroll
     for (int k = 0; k < N; k++) {
-        const float v = (float)abs1(row[k]);
-        const unsigned key = pos < 0 ? (0x80000000u | (__float_as_uint(v) & ~GM) | (GM - (unsigned)r)) : 0u;
-        const unsigned kmax = group_max<G>(key);
-        const int p = (int)(GM - (kmax & GM));
-        sing |= ((kmax & 0x7fffffffu & ~GM) == 0u);
-        pl[k] = p;
-        if (r == p) {
+        pl[k] = 0;
+        if (k < nrt) {
+            const float v = (float)abs1(row[k]);
+            const unsigned key = pos < 0 ? (0x80000000u | (__float_as_uint(v) & ~GM) | (GM - (unsigned)r)) : 0u;
+            const unsigned kmax = group_max<G>(key);
+            const int p = (int)(GM - (kmax & GM));
+            sing |= ((kmax & 0x7fffffffu & ~GM) == 0u);
+            pl[k] = p;
+            if (r == p) {
 #pragma unroll
-            for (int c = k; c <= N; c++) stl(piv, c, row[c]);
+                for (int c = k; c <= N; c++) stl(piv, c, row[c]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            cx<R> P[N + 1];
+#pragma unroll
+            for (int c = k; c <= N; c++) P[c] = ldl(piv, c);
+            const cx<R> inv = crecip(P[k]);
+            const bool piv = (r == p);
+            pos = piv ? k : pos;
+            inv_own = csel(piv, inv, inv_own);
+            cx<R> l = cmul(row[k], inv);
+            l = csel(pos < 0, l, cx<R>{R(0), R(0)});
+#pragma unroll
+            for (int c = k + 1; c <= N; c++) row[c] = cfms(l, P[c], row[c]);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        cx<R> P[N + 1];
-#pragma unroll
-        for (int c = k; c <= N; c++) P[c] = ldl(piv, c);
-        const cx<R> inv = crecip(P[k]);
-        const bool piv = (r == p);
-        pos = piv ? k : pos;
-        inv_own = csel(piv, inv, inv_own);
-        cx<R> l = cmul(row[k], inv);
-        l = csel(pos < 0, l, cx<R>{R(0), R(0)});
-#pragma unroll
-        for (int c = k + 1; c <= N; c++) row[c] = cfms(l, P[c], row[c]);
     }
     cx<R> b = row[N];
     dxr = {R(0), R(0)};
     nd = R(0);
 #pragma unroll
     for (int k = N - 1; k >= 0; k--) {
-        const cx<R> xk = bcast(cmul(b, inv_own), base + pl[k]);
-        dxr = csel(r == k, xk, dxr);
-        nd = fma(xk.re, xk.re, fma(xk.im, xk.im, nd));
-        const bool above = pos < k;
-        b = csel(above, cfms(row[k], xk, b), b);
+        if (k < nrt) {
+            const cx<R> xk = bcast(cmul(b, inv_own), base + pl[k]);
+            dxr = csel(r == k, xk, dxr);
+            nd = fma(xk.re, xk.re, fma(xk.im, xk.im, nd));
+            const bool above = pos < k;
+            b = csel(above, cfms(row[k], xk, b), b);
+        }
     }
     return sing;
 }
@@ -561,65 +586,157 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 }
 
 // ---------------------------------------------------------------- term lists
-// Layout for any system of degree <= 2 with n <= kTermsN (section 6: a term table
-// per equation).  Equation r has T slots; slot k holds one term c_k x_a x_b with
-// its variables packed as a | b << 8 (0xFF: no factor, so 0xFFFF is a constant,
-// and an unused slot is 0xFFFF with c_k = 0).  Kernels run with kTermsN rows per
-// group: lanes r >= n carry the identity row e_r with a zero right-hand side,
-// so their unknowns stay 0 and the LU is the one of the n x n system.
+// Layout for sparse systems (section 6: a term table per equation).  Equation r
+// has T slots; slot k holds one term c_k m_k(x).  Three kernel kinds:
+//   * quadratic (kTermsQ16): degree <= 2, n <= 16; the slot's variables are
+//     packed as a | b << 8 in 16 bits (0xFF: no factor, so 0xFFFF is a constant
+//     and an unused slot is 0xFFFF with c_k = 0);
+//   * general degree (kTermsG16: n <= 16; kTermsG20: n <= 20): the monomial's
+//     factors, with repetition, in the bytes of a 64-bit word, lowest byte first
+//     (0xFF: no factor, so at most 8 factors), plus a per-slot degree that is the
+//     largest over the equations (equations keep their terms in decreasing
+//     degree, so that maximum is tight), on which the kernels branch uniformly.
+// Kernels run with NM rows per group of G lanes: lanes r >= n carry the
+// identity row e_r with a zero right-hand side and never pivot.
+enum TermKind { kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermKinds = 3 };
+
+template <int TK>
+struct TermCfg {
+    static constexpr int NM = TK == kTermsG20 ? 20 : 16;  // rows of the group solver
+    static constexpr int G = TK == kTermsG20 ? 32 : 16;   // lanes per path
+    static constexpr bool GEN = TK != kTermsQ16;          // general-degree slots
+    static constexpr int MAXD = GEN ? 8 : 2;               // factors per slot
+};
+
 constexpr int kTermsN = 16;
 
-// LDS of one wavefront for the term-list layout: the group's stage point (one
-// component per lane) and each lane's row accumulator, room for FP64.
-constexpr int kTermsLdsCx = 64 + 64 * (kTermsN + 1);
+// LDS of one wavefront for a term-list kind: the groups' stage points (one
+// component per lane) and the owned rows' accumulators (NM rows of NM entries,
+// stride NM + 1 against bank conflicts), room for FP64.
+template <int NM, int G>
+constexpr int terms_lds_cx() { return 64 + (64 / G) * NM * (NM + 1); }
 
+// Row accumulator of lane r (r < NM) of the group at lane `base`.
+template <int NM, int G, typename R>
+__device__ __forceinline__ lds_tab<R> terms_row_acc(lds_tab<R> xs, int base, int r)
+{
+    return xs + 64 + ((base / G) * NM + r) * (NM + 1);
+}
+
+// Term c x_{f_0} ... x_{f_{D-1}} of a general-degree slot (factor i in byte i of
+// v; 0xFF: none, value 1).  Adds cr m(x) to F and, for each factor f_i,
+// ct dm/dx_{f_i} contributions to the row accumulator rb: the derivative of the
+// product along factor i is the product of the other factors, taken as prefix
+// (factors before i) times suffix (factors after i) products.
+template <int D, int NM, typename R>
+__device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<R> ct, lds_tab<R> xg, lds_tab<R> rb,
+                                             cx<R> &F)
+{
+    const cx<R> one = {R(1), R(0)};
+    int f[D];
+    cx<R> xv[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        f[i] = (int)((v >> (8 * i)) & 0xFFull);
+        xv[i] = f[i] < NM ? ldl(xg, f[i]) : one;
+    }
+    cx<R> P[D];  // P[i] = x_{f_0} ... x_{f_{i-1}}
+    P[0] = one;
+#pragma unroll
+    for (int i = 1; i < D; i++) P[i] = i == 1 ? xv[0] : cmul(P[i - 1], xv[i - 1]);
+    F = cfma(cr, D == 1 ? xv[0] : cmul(P[D - 1], xv[D - 1]), F);
+    cx<R> S = one;  // x_{f_{i+1}} ... x_{f_{D-1}}
+#pragma unroll
+    for (int i = D - 1; i >= 0; i--) {
+        const cx<R> dm = i == 0 ? S : (i == D - 1 ? P[i] : cmul(P[i], S));
+        if (f[i] < NM) stl(rb, f[i], cfma(ct, dm, ldl(rb, f[i])));
+        if (i > 0) S = i == D - 1 ? xv[i] : cmul(S, xv[i]);
+    }
+}
+
+// Coefficient of slot k at t (ct, for the Jacobian and H) and on the right-hand
+// side (cr): c1 for total degree; (1-t) c0 + t c1, and c1 - c0 for H_t in a
+// predictor stage, for a parameter homotopy.
+template <typename R, bool PARAM>
+__device__ __forceinline__ void slot_coefs(const R *c1, const R *c0, int k, R t, R omt, bool pred, cx<R> &ct,
+                                           cx<R> &cr)
+{
+    const cx<R> c = {c1[2 * k], c1[2 * k + 1]};
+    ct = c;
+    cr = c;
+    if constexpr (PARAM) {
+        const cx<R> s = {c0[2 * k], c0[2 * k + 1]};
+        ct = {fma(t, c.re, omt * s.re), fma(t, c.im, omt * s.im)};
+        cr = pred ? cx<R>{c.re - s.re, c.im - s.im} : ct;
+    }
+}
 
 // Row r of [H_x | rhs] from the lane's term list (vars, c1 and, for a parameter
 // homotopy, c0: the equation's T slots), at the point held in xg (component j
 // at xg[j]); rb is the lane's row accumulator.  Total degree: H = (1-t) gam G +
-// t F with G_r = x_r^d - 1; parameter: H = F(x; (1-t) c0 + t c1), H_t =
-// F(x; c1 - c0).  The right-hand side is -H_t for a predictor stage, -H else.
-template <int NM, typename R, bool PARAM>
-__device__ __forceinline__ void build_row_terms(const unsigned short *vars, int T, const R *c1, const R *c0,
-                                                lds_tab<R> xg, lds_tab<R> rb, int r, bool own, bool d2,
-                                                cx<R> gam, cx<R> xr, R t, bool pred, cx<R> (&row)[NM + 1])
+// t F with G_r = x_r^dg - 1 (dg: the degree of equation r); parameter: H =
+// F(x; (1-t) c0 + t c1), H_t = F(x; c1 - c0).  The right-hand side is -H_t for
+// a predictor stage, -H else.
+template <int TK, typename R, bool PARAM>
+__device__ __forceinline__ void build_row_terms(const void *vars, const int *sdeg, int T, const R *c1, const R *c0,
+                                                lds_tab<R> xg, lds_tab<R> rb, int r, bool own, int dg,
+                                                cx<R> gam, cx<R> xr, R t, bool pred,
+                                                cx<R> (&row)[TermCfg<TK>::NM + 1])
 {
+    constexpr int NM = TermCfg<TK>::NM;
     const cx<R> zero = {R(0), R(0)}, one = {R(1), R(0)};
+    if (own) {
 #pragma unroll
-    for (int j = 0; j < NM; j++) stl(rb, j, zero);
+        for (int j = 0; j < NM; j++) stl(rb, j, zero);
+    }
     const R omt = R(1) - t;
     cx<R> F = zero;
-    const int cnt = own ? T : 0;
-    for (int k = 0; k < cnt; k++) {
-        const unsigned v = vars[k];
-        const int ia = (int)(v & 0xFFu), ib = (int)(v >> 8);
-        const cx<R> c = {c1[2 * k], c1[2 * k + 1]};
-        cx<R> ct = c, cr = c;
-        if constexpr (PARAM) {
-            const cx<R> s = {c0[2 * k], c0[2 * k + 1]};
-            ct = {fma(t, c.re, omt * s.re), fma(t, c.im, omt * s.im)};
-            cr = pred ? cx<R>{c.re - s.re, c.im - s.im} : ct;
+    if constexpr (!TermCfg<TK>::GEN) {
+        const unsigned short *vr = static_cast<const unsigned short *>(vars);
+        const int cnt = own ? T : 0;
+        for (int k = 0; k < cnt; k++) {
+            const unsigned v = vr[k];
+            const int ia = (int)(v & 0xFFu), ib = (int)(v >> 8);
+            cx<R> ct, cr;
+            slot_coefs<R, PARAM>(c1, c0, k, t, omt, pred, ct, cr);
+            const cx<R> xa = ia < NM ? ldl(xg, ia) : one;
+            const cx<R> xb = ib < NM ? ldl(xg, ib) : one;
+            F = cfma(cr, cmul(xa, xb), F);
+            if (ia < NM) stl(rb, ia, cfma(ct, xb, ldl(rb, ia)));
+            if (ib < NM) stl(rb, ib, cfma(ct, xa, ldl(rb, ib)));
         }
-        const cx<R> xa = ia < NM ? ldl(xg, ia) : one;
-        const cx<R> xb = ib < NM ? ldl(xg, ib) : one;
-        F = cfma(cr, cmul(xa, xb), F);
-        if (ia < NM) stl(rb, ia, cfma(ct, xb, ldl(rb, ia)));
-        if (ib < NM) stl(rb, ib, cfma(ct, xa, ldl(rb, ib)));
+    } else if (own) {
+        const unsigned long long *vr = static_cast<const unsigned long long *>(vars);
+        for (int k = 0; k < T; k++) {
+            const int m = __builtin_amdgcn_readfirstlane(sdeg[k]);  // same slot in every lane
+            const unsigned long long v = vr[k];
+            cx<R> ct, cr;
+            slot_coefs<R, PARAM>(c1, c0, k, t, omt, pred, ct, cr);
+            switch (m) {
+            case 0: F = cfma(cr, one, F); break;
+            case 1: term_general<1, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 2: term_general<2, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 3: term_general<3, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 4: term_general<4, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 5: term_general<5, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 6: term_general<6, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 7: term_general<7, NM, R>(v, cr, ct, xg, rb, F); break;
+            default: term_general<8, NM, R>(v, cr, ct, xg, rb, F); break;
+            }
+        }
     }
+    if (own) {
 #pragma unroll
-    for (int j = 0; j < NM; j++) row[j] = ldl(rb, j);
+        for (int j = 0; j < NM; j++) row[j] = ldl(rb, j);
+    }
     if constexpr (PARAM) {
         row[NM] = {-F.re, -F.im};
     } else {
-        cx<R> Gv, dG;
-        if (d2) {
-            Gv = cmul(xr, xr);
-            Gv.re -= R(1);
-            dG = {R(2) * xr.re, R(2) * xr.im};
-        } else {
-            Gv = {xr.re - R(1), xr.im};
-            dG = one;
-        }
+        cx<R> p = one;  // x_r^(dg-1)
+        for (int e = 1; e < dg; e++) p = cmul(p, xr);
+        cx<R> Gv = cmul(p, xr);
+        Gv.re -= R(1);
+        const cx<R> dG = {R(dg) * p.re, R(dg) * p.im};
         const cx<R> gG = cmul(gam, Gv);
         const cx<R> gdG = cmul(gam, dG);
 #pragma unroll
@@ -640,26 +757,26 @@ __device__ __forceinline__ void build_row_terms(const unsigned short *vars, int 
 
 // One stage of every group in precision R on the term-list layout (see
 // stage_solve): the lanes publish their components of the stage point in LDS,
-// build their rows and solve.  Whole wavefront active.
-template <int NM, int G, typename R, bool PARAM>
-__device__ __forceinline__ bool stage_solve_terms(const unsigned short *vars, int T, const R *p1, const R *p0,
-                                                  void *ldsv, int lane, int r, int base, bool own, bool d2,
+// build their rows and solve the n x n system.  Whole wavefront active.
+template <int TK, typename R, bool PARAM>
+__device__ __forceinline__ bool stage_solve_terms(const void *vars, const int *sdeg, int T, const R *p1, const R *p0,
+                                                  void *ldsv, int lane, int r, int base, bool own, int n, int dg,
                                                   cx<R> gam, cx<double> xe, double te, bool pred, cx<double> &d,
                                                   double &nd)
 {
+    constexpr int NM = TermCfg<TK>::NM, G = TermCfg<TK>::G;
     const lds_tab<R> xs = (lds_tab<R>)(cx<R> *)ldsv;
-    const lds_tab<R> rows = xs + 64;
     const cx<R> xo = own ? cx<R>{R(xe.re), R(xe.im)} : cx<R>{R(0), R(0)};
     stl(xs, lane, xo);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     cx<R> row[NM + 1];
-    build_row_terms<NM, R, PARAM>(vars, T, p1, p0, xs + base, rows + lane * (NM + 1), r, own, d2, gam, xo, R(te),
-                                  pred, row);
+    build_row_terms<TK, R, PARAM>(vars, sdeg, T, p1, p0, xs + base, terms_row_acc<NM, G>(xs, base, own ? r : 0), r,
+                                  own, dg, gam, xo, R(te), pred, row);
     cx<R> dxr;
     R nd2;
-    const bool sing = group_solve<NM, G, R>(row, r, base, dxr, nd2);
+    const bool sing = group_solve<NM, G, R>(row, r, base, dxr, nd2, n);
     d = {(double)dxr.re, (double)dxr.im};
     nd = (double)nd2;
     return sing;
@@ -667,15 +784,15 @@ __device__ __forceinline__ bool stage_solve_terms(const unsigned short *vars, in
 
 // The term-list FP64 stage of the mixed-precision tracker, not inlined (see
 // stage64_dense).
-template <int NM, int G, bool PARAM>
-__device__ __attribute__((noinline)) StageOut stage64_terms(const unsigned short *vars, int T, const double *q1,
-                                                             const double *q0, void *ldsv, int lane, int r, int base,
-                                                             bool own, bool d2, cx<double> gam64, cx<double> xe,
-                                                             double te, bool pred)
+template <int TK, bool PARAM>
+__device__ __attribute__((noinline)) StageOut stage64_terms(const void *vars, const int *sdeg, int T,
+                                                             const double *q1, const double *q0, void *ldsv, int lane,
+                                                             int r, int base, bool own, int n, int dg,
+                                                             cx<double> gam64, cx<double> xe, double te, bool pred)
 {
     StageOut o;
-    o.sing = stage_solve_terms<NM, G, double, PARAM>(vars, T, q1, q0, ldsv, lane, r, base, own, d2, gam64, xe, te,
-                                                     pred, o.d, o.nd);
+    o.sing = stage_solve_terms<TK, double, PARAM>(vars, sdeg, T, q1, q0, ldsv, lane, r, base, own, n, dg, gam64, xe,
+                                                  te, pred, o.d, o.nd);
     return o;
 }
 
@@ -700,12 +817,14 @@ __device__ __attribute__((noinline)) StageOut stage64_terms(const unsigned short
 // accepted point, h reset to h0 after a failure) -- the wavefront runs the FP64
 // stage, with tables read from global memory, only while one of its groups
 // needs it.
-template <int N, int G, typename R, bool PARAM, typename Src, bool TERMS = false>
+template <int N, int G, typename R, bool PARAM, typename Src, int TK = -1>
 __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *lds)
 {
-    static_assert(G == 4 || G == 8 || G == 16, "group size");
+    constexpr bool TERMS = TK >= 0;
+    constexpr int TKc = TERMS ? TK : 0;
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32, "group size");
     static_assert(N <= G, "one row per lane");
-    static_assert(!TERMS || N == kTermsN, "term lists run with kTermsN rows");
+    static_assert(!TERMS || (N == TermCfg<TKc>::NM && G == TermCfg<TKc>::G), "term-list kind");
     constexpr bool R64 = sizeof(R) == 8;
     // dense layout: n = N and T = C(N+2, 2) slots per equation; term lists: runtime
     const int nn = TERMS ? a.n : N;
@@ -716,13 +835,21 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     const int base = lane - r;
     const bool own = r < nn;      // lane holds a component of the path state
     const int rr = own ? r : 0;   // table row the lane reads (padding lanes: row 0)
-    const unsigned short *vrow = TERMS ? a.vars + (size_t)rr * T : nullptr;
+    const void *vrow = nullptr;
+    if constexpr (TERMS) {
+        if constexpr (TermCfg<TKc>::GEN)
+            vrow = static_cast<const unsigned long long *>(a.vars) + (size_t)rr * T;
+        else
+            vrow = static_cast<const unsigned short *>(a.vars) + (size_t)rr * T;
+    }
     // mixed precision: FP64 corrector right-hand side around the FP32 solves
     const bool ir = !R64 && a.ir;
     const long long total = a.total;
     const TrackState S = a.s;
     const double pred_tol = a.pred_tol;
     const bool d2 = own && ((a.deg2 >> r) & 1u);
+    // term lists: degree of the lane's equation (total-degree start system)
+    const int dg = !own ? 1 : (TERMS && TermCfg<TKc>::GEN && a.eqdeg) ? a.eqdeg[r] : (d2 ? 2 : 1);
 
     const lds_tab<R> cl0 = (lds_tab<R>)lds + rr;
     // parameter homotopy: the lane's start rows (FP64 ones for the FP64 stage)
@@ -877,8 +1004,8 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
             else
                 asm volatile("" : "+v"(cl));
             if constexpr (TERMS)
-                sing = stage_solve_terms<N, G, R, PARAM>(vrow, T, p1, p0, lds, lane, r, base, own, d2, gam, xe, te,
-                                                         pred, d, nd2);
+                sing = stage_solve_terms<TKc, R, PARAM>(vrow, a.sdeg, T, p1, p0, lds, lane, r, base, own, nn, dg,
+                                                        gam, xe, te, pred, d, nd2);
             else
                 sing = stage_solve<N, G, R, PARAM>(LdsRow<N, R>{cl}, p0, p1, r, base, d2, gam, gam64, xe, te, pred,
                                                    ir, d, nd2);
@@ -889,7 +1016,8 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 asm volatile("" : "+v"(q0), "+v"(q1));
                 StageOut o;
                 if constexpr (TERMS)
-                    o = stage64_terms<N, G, PARAM>(vrow, T, q1, q0, lds, lane, r, base, own, d2, gam64, xe, te, pred);
+                    o = stage64_terms<TKc, PARAM>(vrow, a.sdeg, T, q1, q0, lds, lane, r, base, own, nn, dg, gam64, xe,
+                                                  te, pred);
                 else
                     o = stage64_dense<N, G, PARAM>(q0, q1, r, base, d2, gam64, xe, te, pred);
                 if (p64) {

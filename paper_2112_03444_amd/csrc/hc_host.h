@@ -72,7 +72,12 @@ struct hc_system {
     double *d_term_const = nullptr;
     int *d_map_ptr = nullptr, *d_map_col = nullptr;
     double *d_map_val = nullptr;
-    unsigned short *d_vars = nullptr;  // term lists: variables of every slot
+    void *d_vars = nullptr;   // term lists: variables of every slot (16- or 64-bit entries)
+    int tk = 0;               // term lists: kernel kind (0: degree <= 2, n <= 16; 1: any degree,
+                              //   n <= 16; 2: any degree, n <= 20)
+    int max_deg = 0;          // largest term degree
+    int *d_sdeg = nullptr;    // general-degree kinds: [T] largest degree of each slot
+    int *d_eqdeg = nullptr;   // general-degree kinds: [n] equation degrees
 };
 
 struct hc_ctx {

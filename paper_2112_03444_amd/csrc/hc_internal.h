@@ -10,6 +10,7 @@
 namespace hcx {
 
 constexpr int kMaxN = HC_MAX_N;
+constexpr int kMaxTermDeg = 8;  // factors per term-list slot (general-degree kinds)
 
 // Terms of one dense quadratic equation in n unknowns: 1, x_1..x_n, x_a x_b (a <= b).
 __host__ __device__ constexpr int dense_terms(int n) { return 1 + n + n * (n + 1) / 2; }
@@ -66,6 +67,7 @@ struct InitArgs {
     int n, n_start;
     long long total;
     unsigned deg2;            // bit i: equation i has degree 2 (else 1)
+    const int *eqdeg;         // or [n] equation degrees (any degree; overrides deg2)
     const double *start;      // [n_start][n][2] or null (total-degree points)
     double h0;
     TrackState s;
@@ -105,8 +107,11 @@ struct TrackArgs {
     TrackState s;
     unsigned *n_suspended;    // paths left RUNNING by launch_steps
     unsigned *head;           // k_track_grp: next work item (zeroed before each launch)
-    const unsigned short *vars;  // term-list layout: [n][n_tslots] variables a | b << 8
+    const void *vars;         // term-list layout: [n][n_tslots] slot variables (16-bit a | b << 8,
+                              //   or 64-bit factor bytes for the general-degree kinds)
     int n_tslots;             // term-list layout: slots per equation
+    const int *sdeg;          // general-degree kinds: [n_tslots] largest degree of each slot
+    const int *eqdeg;         // general-degree kinds: [n] degree of each equation
     unsigned long long *stage_count;  // or null: stages of active lanes, summed (lane tracker:
                                       // one counter; group tracker: [FP32, FP64] stages)
 };
@@ -125,7 +130,8 @@ struct RefineArgs {
     hc_track_info *info;      // [total] or null
     int n;                    // term-list layout: unknowns,
     int n_tslots;             //   slots per equation
-    const unsigned short *vars;  //   and the slots' variables
+    const void *vars;         //   the slots' variables
+    const int *sdeg;          //   and, general degree, the slots' degrees
 };
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
@@ -154,13 +160,28 @@ hipError_t launch_fill_u32(unsigned *p, unsigned value, int count, hipStream_t s
 hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, hipStream_t st);
 int group_lanes(int n);
 
-// Term-list layout (hc_track_terms.hip): 16 lanes per path, n <= 16.
-hipError_t launch_track_terms(bool fp32, const TrackArgs &a, hipStream_t st);
-hipError_t launch_track_queue_terms(bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,
+// Term-list layout (hc_terms_impl.h): kind tk = 0 (degree <= 2, n <= 16),
+// 1 (any degree <= 8, n <= 16) or 2 (any degree <= 8, n <= 20); 16 lanes per
+// path for kinds 0 and 1, 32 for kind 2.
+constexpr int kTermKindCount = 3;
+constexpr int term_kind_lanes(int tk) { return tk == 2 ? 32 : 16; }
+hipError_t launch_track_terms(int tk, bool fp32, const TrackArgs &a, hipStream_t st);
+hipError_t launch_track_queue_terms(int tk, bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,
                                     int n_items, unsigned *head, int n_waves, hipStream_t st);
-int queue_waves_terms(bool fp32, bool param);
-hipError_t launch_refine_terms(const RefineArgs &a, hipStream_t st);
-hipError_t launch_refine_terms_many(const RefineArgs *a, int count, long long max_total, hipStream_t st);
+int queue_waves_terms(int tk, bool fp32, bool param);
+hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st);
+hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long long max_total, hipStream_t st);
+
+// Per-kind entry points (one source file per kind).
+template <int TK>
+hipError_t launch_track_terms_k(bool fp32, const TrackArgs &a, hipStream_t st);
+template <int TK>
+hipError_t launch_track_queue_terms_k(bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,
+                                      int n_items, unsigned *head, int n_waves, hipStream_t st);
+template <int TK>
+int queue_waves_terms_k(bool fp32, bool param);
+template <int TK>
+hipError_t launch_refine_terms_k(const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st);
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
 // Batch API: one launch per step over many jobs (argument arrays in device memory).

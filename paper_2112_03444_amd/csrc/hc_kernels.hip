@@ -395,16 +395,26 @@ __device__ __forceinline__ void init_body(const InitArgs &a, long long g)
         }
     } else {
         // total-degree start point b: mixed-radix digits over (d_1..d_n), x_1
-        // least significant; with d_i in {1, 2} the roots of unity are +-1.
+        // least significant, digit k of equation j giving the root of unity
+        // exp(2 pi i k / d_j); with d_j in {1, 2} (deg2 mask) they are +-1.
         long long r = b;
         for (int j = 0; j < a.n; j++) {
-            double v = 1.0;
-            if ((a.deg2 >> j) & 1u) {
-                v = (r & 1) ? -1.0 : 1.0;
+            double vr = 1.0, vi = 0.0;
+            if (a.eqdeg) {
+                const int d = a.eqdeg[j];
+                const long long k = r % d;
+                r /= d;
+                if (2 * k == d) {
+                    vr = -1.0;
+                } else if (k != 0) {
+                    sincospi(2.0 * (double)k / (double)d, &vi, &vr);
+                }
+            } else if ((a.deg2 >> j) & 1u) {
+                vr = (r & 1) ? -1.0 : 1.0;
                 r >>= 1;
             }
-            S.xr[j * a.total + g] = v;
-            S.xi[j * a.total + g] = 0.0;
+            S.xr[j * a.total + g] = vr;
+            S.xi[j * a.total + g] = vi;
         }
     }
     S.t[g] = 0.0;

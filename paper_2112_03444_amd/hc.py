@@ -22,7 +22,7 @@ HC_FP64, HC_MIXED = 0, 1
  HC_T_REFINE_FAILED) = range(7)
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
                 "REFINE_FAILED"]
-HC_MAX_N = 16
+HC_MAX_N = 20
 HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
 
 

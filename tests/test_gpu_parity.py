@@ -217,9 +217,9 @@ def test_path_at_infinity(hc, ctx):
 
 
 def test_load_system_errors(hc, ctx):
-    S17 = hc_inputs.dense_quadratic_system(17)
+    S21 = hc_inputs.dense_quadratic_system(21)
     with pytest.raises(hc.HcError):
-        ctx.load_system(S17)  # n > HC_MAX_N
+        ctx.load_system(S21)  # n > HC_MAX_N
     with pytest.raises(hc.HcError):
         ctx.load_system(hc_inputs.dense_quadratic_system(9), layout=hc.HC_LAYOUT_DENSE)  # dense tables: n <= 8
     with pytest.raises(hc.HcError):

@@ -326,6 +326,44 @@ def test_bezout_count_distinct_verified(n, seed):
     assert np.all(info["residual"] <= 1e-13)
 
 
+def test_quintic_n1_matches_companion_roots():
+    """Degree 5 in one unknown (start system x^5 - 1, five roots of unity): the
+    endpoints are numpy.roots' companion-matrix eigenvalues."""
+    S = hc_inputs.support_system(1, [(5, [0])])
+    rng = np.random.default_rng(44)
+    c = hc_inputs.complex_gaussian(rng, (1, S.n_terms))
+    g = hc_inputs.unit_gammas(rng, 1)
+    ep, st, _ = oracle.track(S, c, g)
+    assert ep.shape[1] == 5 and (st == oracle.SUCCESS).all()
+    coeffs = np.zeros(6, complex)  # highest power first
+    for k in range(S.n_terms):
+        coeffs[5 - S.term_exp[k, 0]] += c[0, k]
+    match_sets(ep[0], np.roots(coeffs)[:, None], 1e-10)
+
+
+@pytest.mark.parametrize("spec,seed", [([(3, [0, 1]), (2, [0, 1])], 45),
+                                       ([(4, [0, 1, 2]), (3, [0, 1, 2]), (2, [0, 1, 2])], 46),
+                                       ([(5, [0, 1]), (1, [0, 1, 2]), (2, [1, 2])], 47)])
+def test_bezout_count_mixed_degrees(spec, seed):
+    """Equations dense on their supports with degrees d_i: prod d_i distinct,
+    verified finite roots (Bezout; generic coefficients)."""
+    n = len(spec)
+    S = hc_inputs.support_system(n, spec)
+    rng = np.random.default_rng(seed)
+    c = hc_inputs.complex_gaussian(rng, (1, S.n_terms))
+    g = hc_inputs.unit_gammas(rng, 1)
+    ep, st, info = oracle.track(S, c, g)
+    bez = int(np.prod([d for d, _ in spec]))
+    assert ep.shape[1] == bez and (st == oracle.SUCCESS).all()
+    for x in ep[0]:
+        F = np_eval(S, c[0], x)
+        den = np.zeros(n)
+        np.add.at(den, S.term_eq, np.abs(c[0]) * np.abs(np.prod(np.power(x[None, :], S.term_exp), 1)))
+        assert np.max(np.abs(F) / den) <= 1e-12
+    d = np.abs(ep[0][:, None, :] - ep[0][None, :, :]).max(-1) + np.eye(bez) * 1e9
+    assert d.min() > 1e-6
+
+
 def test_config1_roots_polish_in_50_digits():
     mpmath = pytest.importorskip("mpmath")
     S, c, g = hc_inputs.workload("dense3_single")
