@@ -53,16 +53,26 @@ def w_stage(n: int) -> int:
     return w_eval(n) + w_lu(n)
 
 
+def w_term(d: int, blend: int) -> int:
+    """Algorithmic FLOPs of one term of degree d: the coefficient blend, the
+    monomial and the products of all but one factor by prefix and suffix
+    products (3d - 5 complex multiplies for d >= 2), F += c m (8) and one
+    multiply-add per factor into the Jacobian row (8 d); a linear term needs no
+    products (its Jacobian entry is c, an add), a constant only the add into F."""
+    if d == 0:
+        return blend + 2
+    if d == 1:
+        return blend + 8 + 2
+    return blend + 6 * (3 * d - 5) + 8 + 8 * d
+
+
 def w_eval_terms(system, param: bool) -> int:
-    """Algorithmic FLOPs of one evaluation of [H_x | rhs] from term lists, per
-    term: blend of the coefficient (parameter homotopy: 6, and 2 for the
-    right-hand side's c1 - c0), the monomial (6 for two factors), F += c m (8),
-    and the Jacobian entries (8 per factor of a degree-2 term, an add for a
-    linear one).  Total degree adds 37 per equation for G, gamma and the blend."""
+    """Algorithmic FLOPs of one evaluation of [H_x | rhs] from term lists: per
+    term w_term (parameter homotopy: 8 for the blend and c1 - c0), plus 37 per
+    equation for G, gamma and the blend under total degree."""
     deg = np.asarray(system.term_exp).sum(axis=1)
     blend = 8 if param else 0
-    per = {0: blend + 2, 1: blend + 8 + 2, 2: blend + 6 + 8 + 16}
-    w = int(sum(per[int(d)] for d in deg))
+    w = int(sum(w_term(int(d), blend) for d in deg))
     if not param:
         w += 37 * int(system.n)
     return w
@@ -169,6 +179,65 @@ def vision_leg(ctx, hc, torch, steps, warmup):
     return out
 
 
+def trifocal_leg(ctx, hc, torch, steps, warmup):
+    """Trifocal pose batch (1024 instances, each solved from the monodromy start
+    set along the family's two-leg parameter path), mixed precision, on device
+    buffers; per step both legs."""
+    import hc_inputs.trifocal as TF
+    dev = torch.device("cuda:0")
+    S = TF.trifocal_system()
+    p0, sols = TF.start_instance()
+    _, _, sc = TF.trifocal_workload("trifocal_batch1024")
+    n_inst, n_start, n = sc["pts"].shape[0], sols.shape[0], S.n
+    mids = np.stack([TF.coefficients(TF.waypoints(p0, p1)[1]) for p1 in sc["pts"]])
+    ends = np.stack([TF.coefficients(p1) for p1 in sc["pts"]])
+    c0 = torch.from_numpy(TF.coefficients(p0)).to(dev)
+    cm = torch.from_numpy(mids).to(dev)
+    ce = torch.from_numpy(ends).to(dev)
+    start = torch.from_numpy(sols).to(dev)
+    ep1 = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st1 = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    ep = torch.empty_like(ep1)
+    st = torch.empty_like(st1)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    nan = torch.full_like(ep1, complex(float("nan"), 0.0))
+    sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    wst = w_eval_terms(S, True) + w_lu(n)
+    opts = hc.default_opts(precision="mixed")
+
+    def solve(profs):
+        ctx.track_device(sysh, cm, None, ep1, st1, None, start=start, p_start=c0, opts=opts)
+        if profs is not None:
+            profs.append(ctx.last_profile().as_dict())
+        s2 = torch.where((st1 == hc.HC_T_SUCCESS)[..., None], ep1, nan)
+        ctx.track_device(sysh, ce, None, ep, st, info, start=s2, p_start=cm, opts=opts)
+        if profs is not None:
+            profs.append(ctx.last_profile().as_dict())
+
+    for _ in range(warmup):
+        solve(None)
+    torch.cuda.synchronize()
+    profs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solve(profs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stn = st.cpu().numpy()
+    inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+    out = {"workload": f"trifocal_batch1024: 1024 noisy trifocal-pose instances (n=18, 234 terms of degree <= 5), "
+                       f"two-leg parameter path from a {n_start}-solution monodromy start set "
+                       f"({n_inst * n_start:,} paths per leg)",
+           "mixed": {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+                     "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
+                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
+                     "mean_steps_leg2": float(inf["steps"].mean() + inf["rejects"].mean()),
+                     "roofline": roofline(profs, n, "fp32", wst, "k_track_terms<2,float,true>")}}
+    log(f"bench: trifocal mixed: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s per leg")
+    return out
+
+
 def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="mixed"):
     """Open-loop Poisson arrivals at `rate` requests/s into the serving loop.
     Mix: 40% one dense n = 8 system with 256 paths (the throughput workload's
@@ -235,7 +304,7 @@ def main():
                     help="first copy this many MiB device to device (a known-size kernel that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters in a profiled run)")
     ap.add_argument("--skip", default="",
-                    help="comma-separated legs to skip: per_instance,latency,triangulation,serving")
+                    help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -345,6 +414,11 @@ def main():
         log("bench: 4-view triangulation batch")
         ctx.set_profiling(True)
         extras["triangulation"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
+        ctx.set_profiling(False)
+    if not args.no_extras and "trifocal" not in skip:
+        log("bench: trifocal pose batch")
+        ctx.set_profiling(True)
+        extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1)
         ctx.set_profiling(False)
     if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")

@@ -139,7 +139,12 @@ typedef struct {
     int32_t crossing_check;   /* mixed mode: after refinement, paths of one instance
                                  that ended on the same root (relative distance
                                  <= 1e-8; n_start <= 4096) start over in FP64    (1)     */
-    int32_t reserved;
+    int32_t per_instance_start; /* 1: every instance has its own start system:
+                                 start is [n_inst][n_start][n] and, for
+                                 HC_PARAMETER, p_start [n_inst][n_params] (the
+                                 second leg of a piecewise-linear parameter path
+                                 starts from the first leg's endpoints);
+                                 hc_track and hc_track_device only           (0)     */
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;
@@ -197,9 +202,11 @@ hc_status hc_system_dims(const hc_system *sys, int32_t *n, int64_t *bezout);
 hc_status hc_total_degree_start(const hc_system *sys, int64_t first, int64_t count, hc_c64 *out);
 
 /* Tracks n_start paths for each of n_inst target instances (host buffers).
- *   start:    [n_start][n] start points; NULL for HC_TOTAL_DEGREE (then n_start
+ *   start:    [n_start][n] start points ([n_inst][n_start][n] with
+ *             opts.per_instance_start); NULL for HC_TOTAL_DEGREE (then n_start
  *             must not exceed the Bezout number and path b starts at point b)
- *   p_start:  [n_params] start parameters (HC_PARAMETER only, else NULL)
+ *   p_start:  [n_params] start parameters ([n_inst][n_params] with
+ *             opts.per_instance_start; HC_PARAMETER only, else NULL)
  *   p_target: [n_inst][n_params] target parameters
  *   gamma:    [n_inst] start-system multipliers (HC_TOTAL_DEGREE; NULL = 1)
  *   opts:     NULL = hc_default_opts

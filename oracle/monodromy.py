@@ -16,9 +16,16 @@ published method (Duff, Hill, Jensen, Lee, Leykin, Sommars, IMA J. Numer. Anal.
    solution around the loop; new distinct endpoints join the set;
 3. stop once the set has not grown for `stall` consecutive loops.
 
-Usage (writes tests/golden/start_triang4.npz and prints its sha256):
+Structured families (coefficients that are functions of fewer parameters,
+such as products of image coordinates) loop in parameter space instead; each
+segment follows the family's waypoints so that every leg is a linear
+coefficient homotopy that stays inside the family (`monodromy_family`).
+
+Usage (writes tests/golden/start_triang4.npz or start_trifocal.npz and prints
+its sha256):
 
     python -m oracle.monodromy triang4
+    python -m oracle.monodromy trifocal
 """
 from __future__ import annotations
 
@@ -77,12 +84,22 @@ def _segment(system, c_from, c_to, sols, n_threads):
     return ep[0][st[0] == SUCCESS]
 
 
-def monodromy(system, seed=0, stall=10, max_loops=500, n_threads=None, log=print):
+def _close(sols, orbit):
+    """sols together with their images under `orbit` (a map [N, n] -> [m, N, n]
+    of known symmetries of the family), duplicates removed."""
+    if orbit is None or len(sols) == 0:
+        return sols
+    return distinct_rows(np.concatenate([sols, orbit(sols).reshape(-1, sols.shape[1])]))
+
+
+def monodromy(system, seed=0, stall=10, max_loops=500, n_threads=None, log=print, orbit=None, target=None):
     """(c0, solutions [N, n]) of a generic instance of the linear-coefficient
-    family with the support of `system`."""
+    family with the support of `system`.  `orbit`, if given, maps solutions to
+    the other members of their symmetry orbits (applied to every new solution);
+    the loop also stops once `target` solutions are known."""
     rng = np.random.default_rng(seed)
     c0, x0 = fabricate_pair(system, rng)
-    sols = x0[None, :]
+    sols = _close(x0[None, :], orbit)
     quiet = 0
     t0 = time.time()
     for loop in range(max_loops):
@@ -90,14 +107,54 @@ def monodromy(system, seed=0, stall=10, max_loops=500, n_threads=None, log=print
         xa = _segment(system, c0, ca, sols, n_threads)
         xb = _segment(system, ca, cb, xa, n_threads)
         back = _segment(system, cb, c0, xb, n_threads)
-        merged = distinct_rows(np.concatenate([sols, back])) if len(back) else sols
+        merged = _close(distinct_rows(np.concatenate([sols, back])), orbit) if len(back) else sols
         grew = len(merged) - len(sols)
         sols = merged
         quiet = 0 if grew > 0 else quiet + 1
         log(f"loop {loop}: {len(sols)} solutions (+{grew}), {time.time() - t0:.0f} s")
-        if quiet >= stall:
+        if quiet >= stall or (target is not None and len(sols) >= target):
             break
     return c0, sols
+
+
+def _path(family, system, p_from, p_to, sols, n_threads):
+    """Endpoints of `sols` carried from parameters p_from to p_to: one linear
+    coefficient homotopy per leg between the family's waypoints (on each leg
+    the coefficients of the family are affine in t, so the path stays in the
+    family)."""
+    pts = family.waypoints(p_from, p_to)
+    for a, b in zip(pts[:-1], pts[1:]):
+        if len(sols) == 0:
+            break
+        sols = _segment(system, family.coef(a), family.coef(b), sols, n_threads)
+    return sols
+
+
+def monodromy_family(family, seed=0, stall=10, max_loops=500, n_threads=None, log=print, target=None):
+    """(p0, solutions [N, n]) of a generic member of a structured parameter
+    family (one whose coefficients are not free: `family` supplies the system,
+    c(p), the waypoints of a path between two parameter points, random
+    parameter points, a fabricated start pair and the solution symmetries).
+    Loops p0 -> pa -> pb -> p0 as in `monodromy`."""
+    system = family.system()
+    rng = np.random.default_rng(seed)
+    p0, x0 = family.fabricate(rng)
+    sols = _close(x0[None, :], family.orbit)
+    quiet = 0
+    t0 = time.time()
+    for loop in range(max_loops):
+        pa, pb = family.random(rng), family.random(rng)
+        xa = _path(family, system, p0, pa, sols, n_threads)
+        xb = _path(family, system, pa, pb, xa, n_threads)
+        back = _path(family, system, pb, p0, xb, n_threads)
+        merged = _close(distinct_rows(np.concatenate([sols, back])), family.orbit) if len(back) else sols
+        grew = len(merged) - len(sols)
+        sols = merged
+        quiet = 0 if grew > 0 else quiet + 1
+        log(f"loop {loop}: {len(sols)} solutions (+{grew}), {time.time() - t0:.0f} s")
+        if quiet >= stall or (target is not None and len(sols) >= target):
+            break
+    return p0, sols
 
 
 def check(system, c0, sols):
@@ -109,6 +166,16 @@ def check(system, c0, sols):
 
 def main(argv):
     name = argv[1] if len(argv) > 1 else "triang4"
+    if name == "trifocal":
+        import hc_inputs.trifocal as TF
+        S = TF.trifocal_system()
+        p0, sols = monodromy_family(TF.Family, seed=4, stall=5)
+        eta, d = check(S, TF.coefficients(p0), sols)
+        print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
+        out = TF.START_FILE
+        np.savez(out, params0=p0, coef0=TF.coefficients(p0), solutions=sols)
+        print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
+        return
     if name != "triang4":
         raise SystemExit(f"unknown family {name}")
     import hc_inputs.vision as V

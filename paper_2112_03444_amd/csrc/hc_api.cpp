@@ -82,6 +82,7 @@ void hc_default_opts(hc_opts *o)
     o->lanes_per_path = 0;
     o->fp64_residual = 0;
     o->crossing_check = 1;
+    o->per_instance_start = 0;
 }
 
 const char *hc_last_error(void) { return last_error(); }
@@ -386,6 +387,8 @@ hc_status hc_total_degree_start(const hc_system *s, int64_t first, int64_t count
 
 static hc_status check_opts(const hc_opts &o)
 {
+    if (o.per_instance_start != 0 && o.per_instance_start != 1)
+        return fail(HC_E_INVALID, "opts.per_instance_start = %d", o.per_instance_start);
     if (o.precision != HC_FP64 && o.precision != HC_MIXED)
         return fail(HC_E_INVALID, "opts.precision = %d", o.precision);
     if (!(o.h0 > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.beta_dec > 0 && o.beta_dec < 1) ||
@@ -500,8 +503,9 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const size_t st_doubles = (size_t)total * (2 * n + 2);
     const size_t st_ints = (size_t)total * 6;
     HIP_TRY(c->state.ensure(st_doubles * 8 + st_ints * 4));
-    // tables: n_inst target instances (+ one start instance for a parameter homotopy)
-    const int n_tab = n_inst + (param ? 1 : 0);
+    // tables: n_inst target instances (+ the start instance(s) of a parameter homotopy)
+    const bool pis = o.per_instance_start != 0;
+    const int n_tab = n_inst + (param ? (pis ? n_inst : 1) : 0);
     const size_t coef64 = (size_t)n_tab * n_slots * 2 * sizeof(double);
     const size_t coef32 = mixed ? (size_t)n_tab * n_slots * 2 * sizeof(float) : 0;
     HIP_TRY(c->coef.ensure(coef64 + coef32));
@@ -553,11 +557,12 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     double *tab64_start = nullptr;
     float *tab32_start = nullptr;
     if (param) {
-        // the start instance's tables go after the n_inst target tables
+        // the start instance's tables (one per instance with per_instance_start)
+        // go after the n_inst target tables
         tab64_start = tab64 + (size_t)n_inst * n_slots * 2;
         tab32_start = tab32 ? tab32 + (size_t)n_inst * n_slots * 2 : nullptr;
         PrepArgs p0 = pa;
-        p0.n_inst = 1;
+        p0.n_inst = pis ? n_inst : 1;
         p0.params = reinterpret_cast<const double *>(p_start);
         p0.out64 = tab64_start;
         p0.out32 = tab32_start;
@@ -572,6 +577,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ia.deg2 = s->deg2;
     ia.eqdeg = eqdeg_of(s);
     ia.start = reinterpret_cast<const double *>(start);
+    ia.start_per_inst = pis ? 1 : 0;
     ia.h0 = o.h0;
     ia.s = S;
     ia.retrack = 0;
@@ -618,6 +624,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     auto run_pass = [&](bool fp32, double t_final, int escalate) -> hc_status {
         ta.coef = fp32 ? (const void *)tab32 : (const void *)tab64;
         ta.coef0 = !param ? nullptr : fp32 ? (const void *)tab32_start : (const void *)tab64_start;
+        ta.coef0_stride = (param && pis) ? (long long)n_slots * 2 : 0;
         ta.coef64 = tab64;
         ta.coef0_64 = tab64_start;
         ta.tau = fp32 ? o.tau32 : o.tau64;
@@ -861,10 +868,11 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     HIP_TRY(hipSetDevice(c->device));
     const int n = s->n;
     // device copies: start, p_target, gamma, endpoints, status, info
-    const size_t b_start = start ? (size_t)n_start * n * sizeof(hc_c64) : 0;
+    const size_t per = (opts && opts->per_instance_start) ? (size_t)n_inst : 1;  // start sets
+    const size_t b_start = start ? per * n_start * n * sizeof(hc_c64) : 0;
     const size_t b_par = (size_t)n_inst * s->n_params * sizeof(hc_c64);
     const size_t b_gam = gamma ? (size_t)n_inst * sizeof(hc_c64) : 0;
-    const size_t b_p0 = p_start ? (size_t)s->n_params * sizeof(hc_c64) : 0;
+    const size_t b_p0 = p_start ? per * s->n_params * sizeof(hc_c64) : 0;
     const size_t b_ep = (size_t)total * n * sizeof(hc_c64);
     const size_t b_st = (size_t)total * sizeof(int32_t);
     const size_t b_inf = info ? (size_t)total * sizeof(hc_track_info) : 0;
@@ -916,6 +924,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     if (rc != HC_OK) return rc;
     if (o.steps_per_launch != 0 || o.lanes_per_path == 1)
         return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: needs steps_per_launch = 0 and lanes_per_path 0/4/8");
+    if (o.per_instance_start)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: per_instance_start is not available in a batch");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool mixed = o.precision == HC_MIXED;
 
@@ -1037,6 +1047,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         ia.deg2 = p.s->deg2;
         ia.eqdeg = eqdeg_of(p.s);
         ia.start = reinterpret_cast<const double *>(p.j->start);
+        ia.start_per_inst = 0;
         ia.h0 = o.h0;
         ia.s = S;
         ia.retrack = 0;

@@ -852,7 +852,8 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     const int dg = !own ? 1 : (TERMS && TermCfg<TKc>::GEN && a.eqdeg) ? a.eqdeg[r] : (d2 ? 2 : 1);
 
     const lds_tab<R> cl0 = (lds_tab<R>)lds + rr;
-    // parameter homotopy: the lane's start rows (FP64 ones for the FP64 stage)
+    // parameter homotopy: the lane's start rows (FP64 ones for the FP64 stage),
+    // per group when every instance has its own start system
     const R *row0 = static_cast<const R *>(a.coef0) + (size_t)rr * T * 2;
     const double *row0_64 = static_cast<const double *>(a.coef0_64) + (size_t)rr * T * 2;
 
@@ -968,6 +969,11 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     const size_t ro = ((size_t)cur_inst * nn + rr) * T * 2;
                     row1 = static_cast<const R *>(a.coef) + ro;
                     if (!R64) row1_64 = static_cast<const double *>(a.coef64) + ro;
+                    if (PARAM && a.coef0_stride) {
+                        const size_t ro0 = (size_t)cur_inst * a.coef0_stride + (size_t)rr * T * 2;
+                        row0 = static_cast<const R *>(a.coef0) + ro0;
+                        if (!R64) row0_64 = static_cast<const double *>(a.coef0_64) + ro0;
+                    }
                     x = own ? cx<double>{S.xr[r * total + g], S.xi[r * total + g]} : cx<double>{0.0, 0.0};
                     t = S.t[g];
                     h = S.h[g];

@@ -68,7 +68,9 @@ struct InitArgs {
     long long total;
     unsigned deg2;            // bit i: equation i has degree 2 (else 1)
     const int *eqdeg;         // or [n] equation degrees (any degree; overrides deg2)
-    const double *start;      // [n_start][n][2] or null (total-degree points)
+    const double *start;      // [n_start][n][2] (per instance: [n_inst][n_start][n][2]) or
+                              // null (total-degree points)
+    int start_per_inst;       // start holds one set of start points per instance
     double h0;
     TrackState s;
     int retrack;              // only reset paths marked kRetrack, in FP64 (escal = 1)
@@ -90,6 +92,7 @@ struct TrackArgs {
     int n;                    // unknowns (the persistent tracker dispatches on it)
     const void *coef;         // [n_inst][n][T][2] in the tracking precision
     const void *coef0;        // parameter homotopy: start tables [n][T][2], else null
+    long long coef0_stride;   // elements between instances' start tables (0: one shared)
     const double *coef64;     // group tracker in mixed mode: FP64 tables for the FP64 stage
     const double *coef0_64;   //   and the FP64 start tables of a parameter homotopy
     const double *gamma;      // [n_inst][2] or null (gamma = 1)

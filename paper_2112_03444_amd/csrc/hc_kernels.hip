@@ -389,9 +389,10 @@ __device__ __forceinline__ void init_body(const InitArgs &a, long long g)
     const TrackState S = a.s;
     if (a.retrack && S.status[g] != kRetrack) return;
     if (a.start) {
+        const long long sb = a.start_per_inst ? g : b;  // g = instance * n_start + b
         for (int j = 0; j < a.n; j++) {
-            S.xr[j * a.total + g] = a.start[(b * a.n + j) * 2];
-            S.xi[j * a.total + g] = a.start[(b * a.n + j) * 2 + 1];
+            S.xr[j * a.total + g] = a.start[(sb * a.n + j) * 2];
+            S.xi[j * a.total + g] = a.start[(sb * a.n + j) * 2 + 1];
         }
     } else {
         // total-degree start point b: mixed-radix digits over (d_1..d_n), x_1

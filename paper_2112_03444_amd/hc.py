@@ -10,7 +10,11 @@ import ctypes
 import os
 from typing import Optional
 
+import contextlib
+
 import numpy as np
+
+_nullcontext = contextlib.nullcontext
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhc.so")
@@ -47,7 +51,7 @@ class Opts(ctypes.Structure):
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
                  "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual",
-                 "crossing_check", "reserved")]
+                 "crossing_check", "per_instance_start")]
 
 
 class Job(ctypes.Structure):
@@ -258,22 +262,43 @@ class Context:
     def track(self, s: System, p_target, gamma=None, start=None, p_start=None, opts: Optional[Opts] = None,
               n_start: Optional[int] = None):
         """Host-buffer hc_track.  p_target [n_inst, n_params]; gamma [n_inst];
-        start [n_start, n] or None (total-degree points).  Returns numpy
-        (endpoints [n_inst, n_start, n], status [n_inst, n_start], info)."""
+        start [n_start, n] or None (total-degree points).  A start of shape
+        [n_inst, n_start, n] or a p_start of shape [n_inst, n_params] gives every
+        instance its own start system (opts.per_instance_start; the other one is
+        broadcast).  Returns numpy (endpoints [n_inst, n_start, n],
+        status [n_inst, n_start], info)."""
         p = np.ascontiguousarray(p_target, np.complex128)
         if p.ndim == 1:
             p = p[None, :]
         n_inst = p.shape[0]
         g = None if gamma is None else np.ascontiguousarray(
             np.broadcast_to(np.asarray(gamma, np.complex128), (n_inst,)))
-        st = None if start is None else np.ascontiguousarray(start, np.complex128).reshape(-1, s.n)
+        st = None if start is None else np.asarray(start, np.complex128)
+        ps = None if p_start is None else np.asarray(p_start, np.complex128)
+        per_inst = (st is not None and st.ndim == 3) or (ps is not None and ps.ndim == 2)
+        if per_inst:
+            if st is not None:
+                st = st if st.ndim == 3 else np.broadcast_to(st.reshape(-1, s.n), (n_inst,) + st.reshape(-1, s.n).shape)
+                if st.shape[0] != n_inst:
+                    raise ValueError("start must hold one set of start points per instance")
+            if ps is not None:
+                ps = ps if ps.ndim == 2 else np.broadcast_to(ps, (n_inst, ps.shape[0]))
+                if ps.shape[0] != n_inst:
+                    raise ValueError("p_start must hold one parameter vector per instance")
+        if st is not None:
+            if n_start is None:
+                n_start = st.shape[1] if per_inst else st.reshape(-1, s.n).shape[0]
+            st = np.ascontiguousarray(st).reshape(-1, s.n)
         if n_start is None:
-            n_start = s.bezout if st is None else st.shape[0]
-        ps = None if p_start is None else np.ascontiguousarray(p_start, np.complex128)
+            n_start = s.bezout
+        ps = None if ps is None else np.ascontiguousarray(ps)
         ep = np.zeros((n_inst, n_start, s.n), np.complex128)
         status = np.zeros((n_inst, n_start), np.int32)
         info = np.zeros((n_inst, n_start), INFO_DTYPE)
         o = opts if opts is not None else default_opts()
+        if per_inst:
+            o = Opts.from_buffer_copy(o)
+            o.per_instance_start = 1
         _check(lib().hc_track(self.handle, s.handle, _ptr(st), n_start, _ptr(ps), _ptr(p), n_inst, _ptr(g),
                               ctypes.byref(o), _ptr(ep), _ptr(status), _ptr(info)))
         return ep, status, info
@@ -289,11 +314,18 @@ class Context:
             return None if t is None else ctypes.c_void_p(t.data_ptr())
 
         n_inst = p_target.shape[0]
+        per_inst = (start is not None and start.dim() == 3) or (p_start is not None and p_start.dim() == 2)
         if n_start is None:
-            n_start = s.bezout if start is None else start.shape[0]
+            n_start = s.bezout if start is None else start.shape[1 if start.dim() == 3 else 0]
         if stream is None:
             stream = torch.cuda.current_stream()
         o = opts if opts is not None else default_opts()
+        if per_inst:
+            # both start arrays must then be per instance
+            if (start is not None and start.dim() != 3) or (p_start is not None and p_start.dim() != 2):
+                raise ValueError("per-instance start: start [n_inst, n_start, n] and p_start [n_inst, n_params]")
+            o = Opts.from_buffer_copy(o)
+            o.per_instance_start = 1
         _check(lib().hc_track_device(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target),
                                      n_inst, dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
                                      ctypes.c_void_p(stream.cuda_stream)))
@@ -317,6 +349,45 @@ class Context:
                                  dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best)))
         return best
+
+    def track_piecewise(self, s: System, waypoints, start, opts: Optional[Opts] = None):
+        """Parameter homotopy along a piecewise-linear path of coefficient
+        vectors: waypoints[0] [n_params] (shared start instance), then
+        waypoints[1..L] each [n_inst, n_params]; leg l is one hc_track call from
+        waypoints[l-1] to waypoints[l], started at the previous leg's endpoints
+        (per instance from leg 2 on; a path that failed is started at NaN, so it
+        ends at once as non-finite).  Returns the last leg's (endpoints, status,
+        info)."""
+        pts = np.ascontiguousarray(start, np.complex128)
+        c_prev = np.asarray(waypoints[0], np.complex128)
+        ep = st = info = None
+        for c_next in waypoints[1:]:
+            ep, st, info = self.track(s, c_next, start=pts, p_start=c_prev, opts=opts)
+            pts = np.where((st == HC_T_SUCCESS)[..., None], ep, np.nan + 0j)
+            c_prev = np.asarray(c_next, np.complex128)
+        return ep, st, info
+
+    def track_piecewise_device(self, s: System, waypoints, start, endpoints, status, info=None,
+                               opts: Optional[Opts] = None, stream=None):
+        """track_piecewise on device tensors: waypoints as torch complex128
+        tensors ([n_params], then [n_inst, n_params] each), start [n_start, n];
+        endpoints/status/info receive the last leg's results.  The legs run on
+        `stream` back to back (no host synchronisation)."""
+        import torch
+        n_inst = waypoints[1].shape[0]
+        pts = start
+        c_prev = waypoints[0]
+        for li, c_next in enumerate(waypoints[1:]):
+            self.track_device(s, c_next, None, endpoints, status, info, start=pts, p_start=c_prev, opts=opts,
+                              stream=stream)
+            if li + 2 < len(waypoints):
+                with torch.cuda.stream(stream) if stream is not None else _nullcontext():
+                    pts = torch.where((status == HC_T_SUCCESS)[..., None], endpoints,
+                                      torch.full_like(endpoints, complex(float("nan"), 0.0)))
+                c_prev = c_next
+                if c_prev.dim() == 1:
+                    c_prev = c_prev.expand(n_inst, -1).contiguous()
+        return endpoints, status, info
 
     def track_batch_device(self, jobs, opts: Optional[Opts] = None, stream=None):
         """hc_track_batch_device.  jobs: list of dicts with keys sys (System),
