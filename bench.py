@@ -179,16 +179,16 @@ def vision_leg(ctx, hc, torch, steps, warmup):
     return out
 
 
-def trifocal_leg(ctx, hc, torch, steps, warmup):
-    """Trifocal pose batch (1024 instances, each solved from the monodromy start
-    set along the family's two-leg parameter path), mixed precision, on device
-    buffers; per step both legs."""
+def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=128):
+    """Trifocal pose batch (instances of trifocal_batch1024, each solved from the
+    monodromy start set along the family's two-leg parameter path) in both
+    precisions, on device buffers; one step = both legs."""
     import hc_inputs.trifocal as TF
     dev = torch.device("cuda:0")
     S = TF.trifocal_system()
     p0, sols = TF.start_instance()
-    _, _, sc = TF.trifocal_workload("trifocal_batch1024")
-    n_inst, n_start, n = sc["pts"].shape[0], sols.shape[0], S.n
+    _, _, sc = TF.trifocal_workload("trifocal_batch1024", n_inst=n_inst)
+    n_start, n = sols.shape[0], S.n
     mids = np.stack([TF.coefficients(TF.waypoints(p0, p1)[1]) for p1 in sc["pts"]])
     ends = np.stack([TF.coefficients(p1) for p1 in sc["pts"]])
     c0 = torch.from_numpy(TF.coefficients(p0)).to(dev)
@@ -197,44 +197,52 @@ def trifocal_leg(ctx, hc, torch, steps, warmup):
     start = torch.from_numpy(sols).to(dev)
     ep1 = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
     st1 = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info1 = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
     ep = torch.empty_like(ep1)
     st = torch.empty_like(st1)
-    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    info = torch.empty_like(info1)
     nan = torch.full_like(ep1, complex(float("nan"), 0.0))
     sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
     wst = w_eval_terms(S, True) + w_lu(n)
-    opts = hc.default_opts(precision="mixed")
+    out = {"workload": f"trifocal: the first {n_inst} of trifocal_batch1024's noisy trifocal-pose instances "
+                       f"(n=18, 234 terms of degree <= 5), two-leg parameter path from a {n_start}-solution "
+                       f"monodromy start set ({n_inst * n_start:,} paths per leg)"}
+    for mode in ("fp64", "mixed"):
+        opts = hc.default_opts(precision=mode)
 
-    def solve(profs):
-        ctx.track_device(sysh, cm, None, ep1, st1, None, start=start, p_start=c0, opts=opts)
-        if profs is not None:
-            profs.append(ctx.last_profile().as_dict())
-        s2 = torch.where((st1 == hc.HC_T_SUCCESS)[..., None], ep1, nan)
-        ctx.track_device(sysh, ce, None, ep, st, info, start=s2, p_start=cm, opts=opts)
-        if profs is not None:
-            profs.append(ctx.last_profile().as_dict())
+        def solve(profs):
+            ctx.track_device(sysh, cm, None, ep1, st1, info1, start=start, p_start=c0, opts=opts)
+            if profs is not None:
+                profs.append(ctx.last_profile().as_dict())
+            s2 = torch.where((st1 == hc.HC_T_SUCCESS)[..., None], ep1, nan)
+            ctx.track_device(sysh, ce, None, ep, st, info, start=s2, p_start=cm, opts=opts)
+            if profs is not None:
+                profs.append(ctx.last_profile().as_dict())
 
-    for _ in range(warmup):
-        solve(None)
-    torch.cuda.synchronize()
-    profs = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        solve(profs)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    stn = st.cpu().numpy()
-    inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
-    out = {"workload": f"trifocal_batch1024: 1024 noisy trifocal-pose instances (n=18, 234 terms of degree <= 5), "
-                       f"two-leg parameter path from a {n_start}-solution monodromy start set "
-                       f"({n_inst * n_start:,} paths per leg)",
-           "mixed": {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+        for _ in range(warmup):
+            solve(None)
+        torch.cuda.synchronize()
+        profs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            solve(profs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        stn = st.cpu().numpy()
+        legs = {}
+        for name, inf_t in (("leg1", info1), ("leg2", info)):
+            inf = inf_t.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+            legs[name] = {"steps": float(inf["steps"].mean()), "rejects": float(inf["rejects"].mean()),
+                          "newton_its": float(inf["newton_its"].mean()),
+                          "escalated_frac": float(inf["escalated"].mean())}
+        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
                      "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
                      "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
-                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
-                     "mean_steps_leg2": float(inf["steps"].mean() + inf["rejects"].mean()),
-                     "roofline": roofline(profs, n, "fp32", wst, "k_track_terms<2,float,true>")}}
-    log(f"bench: trifocal mixed: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s per leg")
+                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(), "legs": legs,
+                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
+                                          f"k_track_terms<2,{'float' if mode == 'mixed' else 'double'},true>")}
+        log(f"bench: trifocal {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s per leg")
+    out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
     return out
 
 
@@ -303,6 +311,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters in a profiled run)")
+    ap.add_argument("--trifocal-instances", type=int, default=128,
+                    help="instances of the trifocal leg (the full batch is 1024)")
     ap.add_argument("--skip", default="",
                     help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,serving")
     args = ap.parse_args()
@@ -418,7 +428,7 @@ def main():
     if not args.no_extras and "trifocal" not in skip:
         log("bench: trifocal pose batch")
         ctx.set_profiling(True)
-        extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1)
+        extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1, n_inst=args.trifocal_instances)
         ctx.set_profiling(False)
     if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")

@@ -31,7 +31,11 @@ each.  The scale gauge fixes the first point's depth in view 1 to 1.  Unknowns
 
 where rho^(p) is point p's depth in view 1.  Terms have degree up to 5
 (f~^2 rho q q).  Every monomial is even in each quaternion, so q -> -q maps
-solutions to solutions: they come in orbits of four.
+solutions to solutions.  A negative focal length is a rotation of every image
+by pi about its optical axis: with D = diag(-1, -1, 1), (f~, R_k, t_k, rho) ->
+(-f~, D R_k D, D t_k, rho) negates the 16 projection equations and keeps the
+norms, i.e. f~ -> -f~, q = (a, b, c, d) -> (a, -b, -c, d), t -> (-t_x, -t_y,
+t_z).  Solutions come in orbits of eight.
 
 Scene recipe: f ~ U[500, 1500] px, 640 x 480 images, principal point
 (320, 240); cameras 2 and 3 have R = exp([w]_x) with w ~ N(0, 0.2^2 I) and
@@ -285,6 +289,24 @@ def sign_orbit(x: np.ndarray) -> np.ndarray:
     return np.stack(out)
 
 
+def focal_flip(x: np.ndarray) -> np.ndarray:
+    """The image of solution(s) x [..., 18] under f~ -> -f~ (D = diag(-1, -1, 1)
+    applied to the rotations by conjugation and to the translations)."""
+    y = np.array(x, copy=True)
+    y[..., I_F] *= -1
+    for k in (2, 3):
+        y[..., I_Q[k] + 1:I_Q[k] + 3] *= -1
+        y[..., I_T[k]:I_T[k] + 2] *= -1
+    return y
+
+
+def symmetry_orbit(x: np.ndarray) -> np.ndarray:
+    """The eight images of solution(s) x [..., 18] under the sign changes of
+    the two quaternions and the focal flip, [8, ..., 18]."""
+    s = sign_orbit(x)
+    return np.concatenate([s, sign_orbit(focal_flip(x))])
+
+
 TRIFOCAL_WORKLOADS: Dict[str, dict] = {
     # 1024 instances per launch, each tracked from the stored start instance
     "trifocal_batch1024": dict(n_inst=1024, seed=5, sigma=0.5),
@@ -358,4 +380,4 @@ class Family:
     waypoints = staticmethod(waypoints)
     random = staticmethod(random_parameters)
     fabricate = staticmethod(fabricate_pair)
-    orbit = staticmethod(sign_orbit)
+    orbit = staticmethod(symmetry_orbit)

@@ -128,17 +128,20 @@ typedef struct {
     int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end (0) */
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
     int32_t lanes_per_path;   /* 1: one path per lane; 4 or 8: one row of [H_x | rhs]
-                                 per lane, 4 or 8 lanes per path; 0 = autotuned  (0)     */
+                                 per lane, 4 or 8 lanes per path (dense tables);
+                                 term lists take 16 (n <= 16) or 32; 0 = autotuned (0)  */
     int32_t use_graph;        /* hc_track_device: capture the launch sequence in a
                                  hipGraph on the first call and replay it while the
                                  arguments stay the same (needs a non-null stream,
                                  steps_per_launch 0, profiling off)             (0)     */
     int32_t fp64_residual;    /* mixed mode: the FP32 pass's Newton corrector evaluates
-                                 H(x, t) in FP64 at an FP64 point and solves with the
-                                 FP32 LU (iterative refinement)                  (0)     */
+                                 H(x, t) in FP64 at an FP64 point (dense tables: from
+                                 the FP32 coefficients; term lists: from the FP64
+                                 tables) and solves with the FP32 LU (iterative
+                                 refinement)                                      (0)     */
     int32_t crossing_check;   /* mixed mode: after refinement, paths of one instance
                                  that ended on the same root (relative distance
-                                 <= 1e-8; n_start <= 4096) start over in FP64    (1)     */
+                                 <= 1e-8; n_start <= 8192) start over in FP64    (1)     */
     int32_t per_instance_start; /* 1: every instance has its own start system:
                                  start is [n_inst][n_start][n] and, for
                                  HC_PARAMETER, p_start [n_inst][n_params] (the

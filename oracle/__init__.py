@@ -44,6 +44,16 @@ DEFAULTS = dict(h0=0.05, h_min=1e-7, h_max=0.1, beta_inc=2.0, beta_dec=0.5, tau=
                 max_steps=5000, max_refine=10)
 
 
+def default_threads() -> int:
+    """Host threads the tracker uses by default: the cores this process may run
+    on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def default_opts(**kw) -> Opts:
     d = dict(DEFAULTS)
     d.update(kw)
@@ -239,7 +249,7 @@ def track(system, coef1, gamma=None, start=None, coef0=None, kind=TOTAL_DEGREE, 
     status = np.zeros((n_inst, n_start), np.int32)
     info = np.zeros((n_inst, n_start), INFO_DTYPE)
     o = opts if opts is not None else default_opts()
-    nt = n_threads if n_threads is not None else (os.cpu_count() or 1)
+    nt = n_threads if n_threads is not None else default_threads()
     rc = _load().orc_track_batch(ctypes.byref(s.c), kind, _ptr(c0), _ptr(c1), _ptr(g), _ptr(st),
                                  n_start, n_inst, ctypes.byref(o), int(nt), _ptr(ep),
                                  _ptr(status), _ptr(info))

@@ -755,25 +755,76 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
     }
 }
 
+// H_r(x, t) of the lane's equation in FP64 from the FP64 tables (q1, q0) at
+// the point held in xg (FP64, component j at xg[j]): the right-hand side of an
+// FP32 Newton stage with the fp64_residual option (iterative refinement).
+template <int TK, bool PARAM>
+__device__ __forceinline__ cx<double> resid_terms64(const void *vars, int T, const double *q1, const double *q0,
+                                                    lds_tab<double> xg, int dg, cx<double> gam, cx<double> xr,
+                                                    double t)
+{
+    constexpr int NM = TermCfg<TK>::NM;
+    const cx<double> one = {1.0, 0.0};
+    const double omt = 1.0 - t;
+    cx<double> F = {0.0, 0.0};
+    for (int k = 0; k < T; k++) {
+        cx<double> c = {q1[2 * k], q1[2 * k + 1]};
+        if constexpr (PARAM) c = {fma(t, c.re, omt * q0[2 * k]), fma(t, c.im, omt * q0[2 * k + 1])};
+        cx<double> m = one;
+        if constexpr (TermCfg<TK>::GEN) {
+            const unsigned long long v = static_cast<const unsigned long long *>(vars)[k];
+            for (int i = 0; i < 8; i++) {
+                const int f = (int)((v >> (8 * i)) & 0xFFull);
+                if (f >= NM) break;
+                m = cmul(m, ldl(xg, f));
+            }
+        } else {
+            const unsigned v = static_cast<const unsigned short *>(vars)[k];
+            const int ia = (int)(v & 0xFFu), ib = (int)(v >> 8);
+            if (ia < NM) m = ldl(xg, ia);
+            if (ib < NM) m = cmul(m, ldl(xg, ib));
+        }
+        F = cfma(c, m, F);
+    }
+    if constexpr (PARAM) return F;
+    cx<double> p = one;
+    for (int e = 0; e < dg; e++) p = cmul(p, xr);
+    p.re -= 1.0;
+    const cx<double> gG = cmul(gam, p);
+    return {fma(t, F.re, omt * gG.re), fma(t, F.im, omt * gG.im)};
+}
+
 // One stage of every group in precision R on the term-list layout (see
 // stage_solve): the lanes publish their components of the stage point in LDS,
-// build their rows and solve the n x n system.  Whole wavefront active.
+// build their rows and solve the n x n system.  Whole wavefront active.  With
+// ir (R = float), a Newton stage's right-hand side is -H evaluated in FP64
+// from the FP64 tables q1, q0 at the FP64 stage point, which goes to the upper
+// half of the wavefront's LDS slice (the FP32 stage uses the lower half).
 template <int TK, typename R, bool PARAM>
 __device__ __forceinline__ bool stage_solve_terms(const void *vars, const int *sdeg, int T, const R *p1, const R *p0,
                                                   void *ldsv, int lane, int r, int base, bool own, int n, int dg,
                                                   cx<R> gam, cx<double> xe, double te, bool pred, cx<double> &d,
-                                                  double &nd)
+                                                  double &nd, bool ir = false, const double *q1 = nullptr,
+                                                  const double *q0 = nullptr, cx<double> gam64 = {1.0, 0.0})
 {
     constexpr int NM = TermCfg<TK>::NM, G = TermCfg<TK>::G;
     const lds_tab<R> xs = (lds_tab<R>)(cx<R> *)ldsv;
     const cx<R> xo = own ? cx<R>{R(xe.re), R(xe.im)} : cx<R>{R(0), R(0)};
     stl(xs, lane, xo);
+    const bool use_ir = sizeof(R) == 4 && ir && !pred;
+    const lds_tab<double> x64 =
+        (lds_tab<double>)(cx<double> *)((char *)ldsv + (size_t)terms_lds_cx<NM, G>() * sizeof(cx<float>));
+    if (use_ir) stl(x64, lane, own ? xe : cx<double>{0.0, 0.0});
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     cx<R> row[NM + 1];
     build_row_terms<TK, R, PARAM>(vars, sdeg, T, p1, p0, xs + base, terms_row_acc<NM, G>(xs, base, own ? r : 0), r,
                                   own, dg, gam, xo, R(te), pred, row);
+    if (use_ir && own) {
+        const cx<double> H = resid_terms64<TK, PARAM>(vars, T, q1, q0, x64 + base, dg, gam64, xe, te);
+        row[NM] = {R(-H.re), R(-H.im)};
+    }
     cx<R> dxr;
     R nd2;
     const bool sing = group_solve<NM, G, R>(row, r, base, dxr, nd2, n);
@@ -1011,7 +1062,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 asm volatile("" : "+v"(cl));
             if constexpr (TERMS)
                 sing = stage_solve_terms<TKc, R, PARAM>(vrow, a.sdeg, T, p1, p0, lds, lane, r, base, own, nn, dg,
-                                                        gam, xe, te, pred, d, nd2);
+                                                        gam, xe, te, pred, d, nd2, ir, row1_64, row0_64, gam64);
             else
                 sing = stage_solve<N, G, R, PARAM>(LdsRow<N, R>{cl}, p0, p1, r, base, d2, gam, gam64, xe, te, pred,
                                                    ir, d, nd2);

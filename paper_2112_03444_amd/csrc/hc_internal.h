@@ -27,7 +27,7 @@ constexpr int kRunning = -1;  // between launches or at the FP32/FP64 hand-over
 constexpr int kReached = -2;  // at t = 1, waiting for refinement
 constexpr int kDone = -3;     // refined; a re-tracking pass leaves it alone
 constexpr int kRetrack = -4;  // endpoint coincides with another: start over in FP64
-constexpr int kDedupMax = 4096;  // largest n_start the crossing check handles
+constexpr int kDedupMax = 8192;  // largest n_start the crossing check handles
 
 // Mixed precision on the group trackers: 1 = a failed FP32 path goes on in FP64
 // inside the same launch; 0 = it goes back to RUNNING and a second (FP64) launch

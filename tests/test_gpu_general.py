@@ -108,6 +108,20 @@ def test_parameter_homotopy_general(hc, ctx, name, precision):
     assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
 
 
+@pytest.mark.parametrize("name", ["cubic3", "mixed5", "deg5_n18"])
+def test_fp64_residual_general(hc, ctx, name):
+    """Mixed mode with the FP64 Newton right-hand side (fp64_residual) on the
+    general-degree kinds, total degree: the same root sets as the oracle."""
+    n, spec = SPECS[name]
+    S, coef, gam = hc_inputs.support_instances(n, spec, 2, seed=6600 + n)
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(precision="mixed", fp64_residual=1))
+    oep, ost, _ = oracle.track(S, coef, gam)
+    for i in range(2):
+        check_parity(ep[i], st[i], oep[i], ost[i], hc)
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
+
+
 def test_start_points_of_any_degree(hc, ctx):
     """The device's total-degree start points (roots of unity, mixed radix over
     the equations) equal hc_total_degree_start's, so supplying them changes

@@ -107,6 +107,42 @@ def test_triangulation_parity(hc, ctx, triang, precision):
     assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
 
 
+def check_paths_where_both_succeed(ep_g, st_g, res_g, ep_o, st_o, hc, rel=REL, max_frac=0.01):
+    """Path-by-path parity for a mode whose failures need not coincide with the
+    oracle's: both sides start path b at the same point, so where both succeed
+    they reach the same root (within rel); where only one succeeds, its root is
+    a valid root (residual <= 1e-10) distinct from every other success of that
+    side; the status disagrees on at most max_frac of the paths."""
+    both = (st_g == hc.HC_T_SUCCESS) & (st_o == oracle.SUCCESS)
+    for b in np.flatnonzero(both):
+        d = np.max(np.abs(ep_g[b] - ep_o[b])) / max(1.0, np.max(np.abs(ep_o[b])))
+        assert d <= rel, (b, d)
+    only_g = (st_g == hc.HC_T_SUCCESS) & ~both
+    only_o = (st_o == oracle.SUCCESS) & ~both
+    assert only_g.sum() + only_o.sum() <= max_frac * len(st_g)
+    assert np.all(res_g[only_g] <= 1e-10)
+    for ep, st, only in ((ep_g, st_g == hc.HC_T_SUCCESS, only_g), (ep_o, st_o == oracle.SUCCESS, only_o)):
+        ok = ep[st]
+        for b in np.flatnonzero(only):
+            d = np.max(np.abs(ok - ep[b]), axis=1) / np.maximum(1.0, np.max(np.abs(ep[b])))
+            assert np.sum(d <= 1e-8) == 1, b  # only itself
+
+
+def test_triangulation_fp64_residual(hc, ctx, triang):
+    """Mixed mode with the FP64 Newton right-hand side from the FP64 tables
+    (fp64_residual) on the quadratic term lists, parameter homotopy.  The FP64
+    right-hand side changes which ill-conditioned paths end at the minimum step,
+    so the comparison is path by path (check_paths_where_both_succeed)."""
+    S, c0, sols, ps = triang
+    _, coef, _ = V.triangulation_instances(2, seed=5250)
+    ep, st, info = ctx.track(ps, coef, start=sols, p_start=c0,
+                             opts=hc.default_opts(precision="mixed", fp64_residual=1))
+    oep, ost, _ = oracle.track(S, coef, start=sols, coef0=c0, kind=oracle.LINEAR)
+    for i in range(2):
+        check_paths_where_both_succeed(ep[i], st[i], info["residual"][i], oep[i], ost[i], hc)
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
+
+
 def test_triangulation_full_batch_sampled(hc, ctx, triang):
     """The full 4096-instance batch (1,212,416 paths) in mixed mode, as the
     benchmark runs it; sampled instances against the oracle, every instance's
