@@ -123,7 +123,9 @@ typedef struct {
     int32_t precision;  /* hc_precision                                        (FP64)  */
     int32_t n_inc;      /* accepted steps before the step grows                (5)     */
     int32_t max_newton; /* corrector iterations per step                       (3)     */
-    int32_t max_steps;  /* accepted + rejected steps per path                  (5000)  */
+    int32_t max_steps;  /* accepted + rejected steps per path; counted afresh
+                           from a hand-over to FP64 (mixed mode) or a
+                           crossing-check restart                             (5000)  */
     int32_t max_refine; /* endpoint Newton iterations                          (10)    */
     int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end (0) */
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */

@@ -967,7 +967,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
         if (!R64 && !p64 && st != HC_T_AT_INFINITY) {
             // mixed precision: the path goes on in FP64 from its last accepted point,
             // in this launch or (escalation off) in the FP64 launch that follows
-            escal = 1;
+            escal = steps + rejects + 1;
             h = a.h0;
             succ = 0;
             if (!kInlineEsc) {
@@ -975,7 +975,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 return;
             }
             p64 = true;
-            if (steps + rejects >= a.max_steps)
+            if (steps_used(steps, rejects, escal) >= a.max_steps)
                 save(HC_T_MAX_STEPS);
             else
                 begin_step();
@@ -1035,7 +1035,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     escal = S.escal[g];
                     p64 = R64 || (kInlineEsc && (escal != 0 || t >= a.t_switch));
                     lsteps = 0;
-                    if (steps + rejects >= a.max_steps)
+                    if (steps_used(steps, rejects, escal) >= a.max_steps)
                         fail(HC_T_MAX_STEPS);
                     else
                         begin_step();
@@ -1162,7 +1162,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 if (a.launch_steps > 0 && lsteps >= a.launch_steps) {
                     if (r == 0) atomicAdd(a.n_suspended, 1u);
                     save(kRunning);
-                } else if (steps + rejects >= a.max_steps) {
+                } else if (steps_used(steps, rejects, escal) >= a.max_steps) {
                     ev = 3;
                     fst = HC_T_MAX_STEPS;
                 } else {

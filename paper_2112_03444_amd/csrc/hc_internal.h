@@ -27,6 +27,15 @@ constexpr int kRunning = -1;  // between launches or at the FP32/FP64 hand-over
 constexpr int kReached = -2;  // at t = 1, waiting for refinement
 constexpr int kDone = -3;     // refined; a re-tracking pass leaves it alone
 constexpr int kRetrack = -4;  // endpoint coincides with another: start over in FP64
+// Path state field `escal`: 0 while a path is tracked in the precision it
+// started in; after a hand-over to FP64 (mixed precision) or a restart of the
+// crossing check, 1 + the path's steps + rejects at that moment, so the FP64
+// tracking gets the whole step budget again.
+__host__ __device__ inline int steps_used(int steps, int rejects, int escal)
+{
+    return steps + rejects - (escal > 0 ? escal - 1 : 0);
+}
+
 constexpr int kDedupMax = 8192;  // largest n_start the crossing check handles
 
 // Mixed precision on the group trackers: 1 = a failed FP32 path goes on in FP64

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_track(const TrackArgs a)
         if (a.escalate && st != HC_T_AT_INFINITY) {
             // FP32 could not finish this path: hand it to FP64 from the last
             // accepted point with a fresh step size.
-            escal = 1;
+            escal = steps + rejects + 1;
             h = a.h0;
             succ = 0;
             st = kRunning;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_track(const TrackArgs a)
         save(st);
     };
     auto start_step = [&]() {
-        if (steps + rejects >= a.max_steps) {
+        if (steps_used(steps, rejects, escal) >= a.max_steps) {
             finish(HC_T_MAX_STEPS);
             return;
         }
@@ -426,7 +426,8 @@ __device__ __forceinline__ void init_body(const InitArgs &a, long long g)
         S.rejects[g] = 0;
         S.nits[g] = 0;
     }
-    S.escal[g] = a.retrack ? 1 : 0;
+    // a restarted path tracks in FP64 with a fresh step budget
+    S.escal[g] = a.retrack ? 1 + S.steps[g] + S.rejects[g] : 0;
     S.status[g] = kRunning;
 }
 
@@ -673,7 +674,7 @@ __device__ __forceinline__ void refine_body(const RefineArgs &a, int block)
         inf.rejects = S.rejects[g];
         inf.newton_its = S.nits[g];
         inf.refine_its = rits;
-        inf.escalated = S.escal[g];
+        inf.escalated = S.escal[g] != 0 ? 1 : 0;
         inf.reserved = 0;
         inf.residual = resid;
         a.info[g] = inf;

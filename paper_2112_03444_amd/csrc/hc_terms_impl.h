@@ -205,7 +205,7 @@ __device__ __forceinline__ void refine_terms_body(const RefineArgs &a, int block
             inf.rejects = S.rejects[g];
             inf.newton_its = S.nits[g];
             inf.refine_its = rits;
-            inf.escalated = S.escal[g];
+            inf.escalated = S.escal[g] != 0 ? 1 : 0;
             inf.reserved = 0;
             inf.residual = res_out;
             a.info[g] = inf;
