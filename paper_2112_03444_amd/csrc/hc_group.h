@@ -405,17 +405,34 @@ __device__ __forceinline__ bool group_solve(cx<R> (&row)[N + 1], int r, int base
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            cx<R> P[N + 1];
-#pragma unroll
-            for (int c = k; c <= N; c++) P[c] = ldl(piv, c);
-            const cx<R> inv = crecip(P[k]);
-            const bool piv = (r == p);
-            pos = piv ? k : pos;
-            inv_own = csel(piv, inv, inv_own);
+            const cx<R> inv = crecip(ldl(piv, k));
+            const bool is_piv = (r == p);
+            pos = is_piv ? k : pos;
+            inv_own = csel(is_piv, inv, inv_own);
             cx<R> l = cmul(row[k], inv);
             l = csel(pos < 0, l, cx<R>{R(0), R(0)});
+            if constexpr ((N + 1) * sizeof(cx<R>) <= 256) {
+                // short rows: the whole pivot row in registers at once
+                cx<R> P[N + 1];
 #pragma unroll
-            for (int c = k + 1; c <= N; c++) row[c] = cfms(l, P[c], row[c]);
+                for (int c = k + 1; c <= N; c++) P[c] = ldl(piv, c);
+#pragma unroll
+                for (int c = k + 1; c <= N; c++) row[c] = cfms(l, P[c], row[c]);
+            } else {
+                // long rows (FP64, N >= 16): the pivot row streams through in
+                // chunks of 4 entries, so it never sits in registers beside the
+                // whole own row (the compiler barrier keeps the loads from all
+                // being hoisted ahead)
+#pragma unroll
+                for (int c0 = k + 1; c0 <= N; c0 += 4) {
+                    cx<R> P[4];
+#pragma unroll
+                    for (int c = c0; c < c0 + 4 && c <= N; c++) P[c - c0] = ldl(piv, c);
+#pragma unroll
+                    for (int c = c0; c < c0 + 4 && c <= N; c++) row[c] = cfms(l, P[c - c0], row[c]);
+                    asm volatile("" ::: "memory");
+                }
+            }
         }
     }
     cx<R> b = row[N];
@@ -624,33 +641,46 @@ __device__ __forceinline__ lds_tab<R> terms_row_acc(lds_tab<R> xs, int base, int
 }
 
 // Term c x_{f_0} ... x_{f_{D-1}} of a general-degree slot (factor i in byte i of
-// v; 0xFF: none, value 1).  Adds cr m(x) to F and, for each factor f_i,
-// ct dm/dx_{f_i} contributions to the row accumulator rb: the derivative of the
-// product along factor i is the product of the other factors, taken as prefix
-// (factors before i) times suffix (factors after i) products.
+// v, in increasing order with repetition; 0xFF: none, value 1).  Adds cr m(x)
+// to F and, for each factor f_i, ct dm/dx_{f_i} to the row accumulator rb: the
+// derivative of the product along factor i is the product of the other
+// factors, taken as prefix (factors before i) times suffix (factors after i)
+// products.  The term's accumulator entries are read together and written
+// together (one LDS round trip per term, not one per factor); a repeated
+// variable's contributions are summed into the last factor of its run, the
+// only one written.
 template <int D, int NM, typename R>
 __device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<R> ct, lds_tab<R> xg, lds_tab<R> rb,
                                              cx<R> &F)
 {
-    const cx<R> one = {R(1), R(0)};
+    const cx<R> one = {R(1), R(0)}, zero = {R(0), R(0)};
     int f[D];
-    cx<R> xv[D];
+    cx<R> xv[D], acc[D];
 #pragma unroll
     for (int i = 0; i < D; i++) {
         f[i] = (int)((v >> (8 * i)) & 0xFFull);
         xv[i] = f[i] < NM ? ldl(xg, f[i]) : one;
+        acc[i] = f[i] < NM ? ldl(rb, f[i]) : zero;
     }
     cx<R> P[D];  // P[i] = x_{f_0} ... x_{f_{i-1}}
     P[0] = one;
 #pragma unroll
     for (int i = 1; i < D; i++) P[i] = i == 1 ? xv[0] : cmul(P[i - 1], xv[i - 1]);
     F = cfma(cr, D == 1 ? xv[0] : cmul(P[D - 1], xv[D - 1]), F);
+    cx<R> dm[D];
     cx<R> S = one;  // x_{f_{i+1}} ... x_{f_{D-1}}
 #pragma unroll
     for (int i = D - 1; i >= 0; i--) {
-        const cx<R> dm = i == 0 ? S : (i == D - 1 ? P[i] : cmul(P[i], S));
-        if (f[i] < NM) stl(rb, f[i], cfma(ct, dm, ldl(rb, f[i])));
+        dm[i] = i == 0 ? S : (i == D - 1 ? P[i] : cmul(P[i], S));
         if (i > 0) S = i == D - 1 ? xv[i] : cmul(S, xv[i]);
+    }
+    cx<R> run = zero;  // contributions of the current run of equal factors
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        run = cfma(ct, dm[i], run);
+        const bool last = i == D - 1 || f[i + 1] != f[i];
+        if (f[i] < NM && last) stl(rb, f[i], cx<R>{acc[i].re + run.re, acc[i].im + run.im});
+        if (last) run = zero;
     }
 }
 
@@ -701,9 +731,16 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
             slot_coefs<R, PARAM>(c1, c0, k, t, omt, pred, ct, cr);
             const cx<R> xa = ia < NM ? ldl(xg, ia) : one;
             const cx<R> xb = ib < NM ? ldl(xg, ib) : one;
+            // both accumulator entries read, then written (x_a^2: one entry)
+            const cx<R> ra = ia < NM ? ldl(rb, ia) : zero;
+            const cx<R> rbb = ib < NM ? ldl(rb, ib) : zero;
             F = cfma(cr, cmul(xa, xb), F);
-            if (ia < NM) stl(rb, ia, cfma(ct, xb, ldl(rb, ia)));
-            if (ib < NM) stl(rb, ib, cfma(ct, xa, ldl(rb, ib)));
+            if (ia == ib) {
+                if (ia < NM) stl(rb, ia, cfma(ct, xa, cfma(ct, xb, ra)));
+            } else {
+                if (ia < NM) stl(rb, ia, cfma(ct, xb, ra));
+                if (ib < NM) stl(rb, ib, cfma(ct, xa, rbb));
+            }
         }
     } else if (own) {
         const unsigned long long *vr = static_cast<const unsigned long long *>(vars);

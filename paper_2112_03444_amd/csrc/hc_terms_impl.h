@@ -319,6 +319,16 @@ hipError_t launch_refine_terms_k(const RefineArgs *a, int count, long long max_t
 
 }  // namespace hcx
 
+// Declaration that another source file instantiates one kind's launchers.
+#define HC_TERMS_EXTERN(TK)                                                                                        \
+    namespace hcx {                                                                                                \
+    extern template hipError_t launch_track_terms_k<TK>(bool, const TrackArgs &, hipStream_t);                    \
+    extern template hipError_t launch_track_queue_terms_k<TK>(bool, bool, const TrackArgs *, const QueueItem *,   \
+                                                              int, unsigned *, int, hipStream_t);                  \
+    extern template int queue_waves_terms_k<TK>(bool, bool);                                                      \
+    extern template hipError_t launch_refine_terms_k<TK>(const RefineArgs *, int, long long, bool, hipStream_t);  \
+    }
+
 // Explicit instantiation of one kind's launchers.
 #define HC_TERMS_INSTANTIATE(TK)                                                                                   \
     namespace hcx {                                                                                                \

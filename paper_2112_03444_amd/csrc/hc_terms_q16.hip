@@ -2,6 +2,8 @@
 #include "hc_terms_impl.h"
 
 HC_TERMS_INSTANTIATE(0)
+HC_TERMS_EXTERN(1)  // hc_terms_g16.hip
+HC_TERMS_EXTERN(2)  // hc_terms_g20.hip
 
 namespace hcx {
 
