@@ -27,10 +27,12 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
-# HBM bytes per tracking launch on dense8_batch512 from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# calibrated on a 512 MiB device copy (profiles/k_track_grp_dense8_batch512.md); they belong to
-# the kernel version profiled there and are not measured live.
-PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 146.9e6, "k_track_grp<8,8,double,false>": 335.9e6}
+# HBM bytes per tracking launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, calibrated on a
+# 512 MiB device copy (profiles/k_track_grp_dense8_batch512.md, k_track_terms_triang4_batch4096.md)
+# for the workloads those runs cover; they belong to the kernel version profiled there and are not
+# measured live.  The trifocal counters cover 32 instances, not the bench's batch: no entry.
+PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 130.3e6, "k_track_grp<8,8,double,false>": 346.7e6,
+                          "k_track_terms<0,float,true>": 1824.6e6, "k_track_terms<0,double,true>": 1720.5e6}
 SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
 
@@ -173,16 +175,19 @@ def vision_leg(ctx, hc, torch, steps, warmup):
                      "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
                      "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
                      "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
-                                          f"k_track_terms<{'float' if mode == 'mixed' else 'double'},true>")}
+                                          f"k_track_terms<0,{'float' if mode == 'mixed' else 'double'},true>")}
         log(f"bench: triangulation {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
     out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
     return out
 
 
-def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=128):
+def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
     """Trifocal pose batch (instances of trifocal_batch1024, each solved from the
-    monodromy start set along the family's two-leg parameter path) in both
-    precisions, on device buffers; one step = both legs."""
+    monodromy start set along the family's two-leg parameter path) on device
+    buffers; one step = both legs.  FP64 on n_inst instances (the full batch by
+    default); mixed precision, which escalates ~45% of these paths to FP64 and
+    so is slower here, on the first n_inst_mixed for comparison.  The warmup
+    runs on 8 instances (the full batch takes about a minute)."""
     import hc_inputs.trifocal as TF
     dev = torch.device("cuda:0")
     S = TF.trifocal_system()
@@ -204,45 +209,47 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=128):
     nan = torch.full_like(ep1, complex(float("nan"), 0.0))
     sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
     wst = w_eval_terms(S, True) + w_lu(n)
-    out = {"workload": f"trifocal: the first {n_inst} of trifocal_batch1024's noisy trifocal-pose instances "
-                       f"(n=18, 234 terms of degree <= 5), two-leg parameter path from a {n_start}-solution "
-                       f"monodromy start set ({n_inst * n_start:,} paths per leg)"}
-    for mode in ("fp64", "mixed"):
+    out = {"workload": f"trifocal_batch1024: noisy trifocal-pose instances (n=18, 234 terms of degree <= 5), "
+                       f"two-leg parameter path from a {n_start}-solution monodromy start set; FP64 on "
+                       f"{n_inst} instances ({n_inst * n_start:,} paths per leg), mixed on the first "
+                       f"{n_inst_mixed}"}
+    for mode, ni in (("fp64", n_inst), ("mixed", n_inst_mixed)):
         opts = hc.default_opts(precision=mode)
 
-        def solve(profs):
-            ctx.track_device(sysh, cm, None, ep1, st1, info1, start=start, p_start=c0, opts=opts)
+        def solve(profs, k):
+            ctx.track_device(sysh, cm[:k], None, ep1[:k], st1[:k], info1[:k], start=start, p_start=c0, opts=opts)
             if profs is not None:
                 profs.append(ctx.last_profile().as_dict())
-            s2 = torch.where((st1 == hc.HC_T_SUCCESS)[..., None], ep1, nan)
-            ctx.track_device(sysh, ce, None, ep, st, info, start=s2, p_start=cm, opts=opts)
+            s2 = torch.where((st1[:k] == hc.HC_T_SUCCESS)[..., None], ep1[:k], nan[:k])
+            ctx.track_device(sysh, ce[:k], None, ep[:k], st[:k], info[:k], start=s2, p_start=cm[:k], opts=opts)
             if profs is not None:
                 profs.append(ctx.last_profile().as_dict())
 
         for _ in range(warmup):
-            solve(None)
+            solve(None, min(8, ni))
         torch.cuda.synchronize()
         profs = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            solve(profs)
+            solve(profs, ni)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        stn = st.cpu().numpy()
+        stn = st[:ni].cpu().numpy()
         legs = {}
         for name, inf_t in (("leg1", info1), ("leg2", info)):
-            inf = inf_t.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+            inf = inf_t[:ni].cpu().numpy().view(hc.INFO_DTYPE).reshape(ni, n_start)
             legs[name] = {"steps": float(inf["steps"].mean()), "rejects": float(inf["rejects"].mean()),
                           "newton_its": float(inf["newton_its"].mean()),
                           "escalated_frac": float(inf["escalated"].mean())}
-        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+        out[mode] = {"instances": ni, "ms_per_step": dt * 1e3, "tracks_per_s": ni * n_start / dt,
+                     "solves_per_s": ni / dt,
                      "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
                      "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
                      "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(), "legs": legs,
                      "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
                                           f"k_track_terms<2,{'float' if mode == 'mixed' else 'double'},true>")}
-        log(f"bench: trifocal {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s per leg")
-    out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
+        log(f"bench: trifocal {mode} ({ni} instances): {dt * 1e3:.1f} ms/step, {ni * n_start / dt:.3e} tracks/s "
+            f"per leg")
     return out
 
 
@@ -311,8 +318,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a known-size kernel that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters in a profiled run)")
-    ap.add_argument("--trifocal-instances", type=int, default=128,
-                    help="instances of the trifocal leg (the full batch is 1024)")
+    ap.add_argument("--trifocal-instances", type=int, default=1024,
+                    help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
                     help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,serving")
     args = ap.parse_args()
@@ -428,7 +435,8 @@ def main():
     if not args.no_extras and "trifocal" not in skip:
         log("bench: trifocal pose batch")
         ctx.set_profiling(True)
-        extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1, n_inst=args.trifocal_instances)
+        extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1, n_inst=args.trifocal_instances,
+                                          n_inst_mixed=min(128, args.trifocal_instances))
         ctx.set_profiling(False)
     if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
