@@ -174,23 +174,25 @@ void hc_destroy(hc_ctx *ctx);
  * section 6, compiled once per family) and uploads its tables to the device.
  * *out stays owned by the context until hc_free_system or hc_destroy.
  * Errors: HC_E_INVALID (malformed description), HC_E_UNSUPPORTED (n > HC_MAX_N,
- * a term of degree > 2, an equation of degree 0), HC_E_OOM, HC_E_DEVICE. */
+ * a term of degree > 8, an equation of degree 0), HC_E_OOM, HC_E_DEVICE. */
 hc_status hc_load_system(hc_ctx *ctx, const hc_system_desc *desc, hc_system **out);
 
 /* Evaluation-table layout of a loaded system. */
 typedef enum {
-    HC_LAYOUT_AUTO = 0,   /* dense tables for n <= 8, term lists above             */
+    HC_LAYOUT_AUTO = 0,   /* dense tables for n <= 8 and degree <= 2, else term
+                             lists                                                */
     HC_LAYOUT_DENSE = 1,  /* every monomial of degree <= 2 gets a table slot
                              (c, L, Q per equation); n <= 8                       */
     HC_LAYOUT_TERMS = 2   /* per equation the list of its own terms (section 6's
-                             term tables), each c x_a x_b; n <= 16              */
+                             term tables): c x_a x_b for degree <= 2 and n <= 16,
+                             else up to 8 factors per term; n <= HC_MAX_N       */
 } hc_layout;
 
 /* hc_load_system with an explicit table layout (hc_load_system uses
  * HC_LAYOUT_AUTO).  Both layouts compute the same homotopy; the term lists do
  * work in proportion to the terms a system has, the dense tables to n^3.
  * Errors: as hc_load_system, and HC_E_UNSUPPORTED for HC_LAYOUT_DENSE with n > 8
- * or an unknown layout. */
+ * or a term of degree > 2, or an unknown layout. */
 hc_status hc_load_system_layout(hc_ctx *ctx, const hc_system_desc *desc, int32_t layout, hc_system **out);
 
 /* Releases a loaded system. */
