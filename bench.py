@@ -253,6 +253,52 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
     return out
 
 
+def lu_leg(ctx, hc, torch, sizes=(4, 8, 12, 16, 20), batches=(1000, 1 << 18), reps=50):
+    """Standalone batched complex FP32 solves (the fused LU of [A | b] plus back
+    substitution), the setting of the paper's batched-solver experiment (1000
+    matrices of 4x4 to 20x20), and a 2^18 batch for throughput; against
+    torch.linalg.solve (the ROCm library's batched LU factorisation and solve)
+    on the same data.  Times from HIP events on the launch stream, mean of
+    `reps` calls.  Algorithmic HBM bytes per system: A and b read, x written, the
+    info word written."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(77)
+    out = {}
+    for batch in batches:
+        for n in sizes:
+            A = torch.from_numpy(((rng.standard_normal((batch, n, n)) + 1j * rng.standard_normal((batch, n, n)))
+                                  / np.sqrt(2)).astype(np.complex64)).to(dev)
+            b = torch.from_numpy(((rng.standard_normal((batch, n)) + 1j * rng.standard_normal((batch, n)))
+                                  / np.sqrt(2)).astype(np.complex64)).to(dev)
+            x = torch.empty_like(b)
+            info = torch.empty((batch,), dtype=torch.int32, device=dev)
+
+            def timed(fn):
+                fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / reps
+
+            ms = timed(lambda: ctx.solve_batched_device(A, b, x, info))
+            ms_lib = timed(lambda: torch.linalg.solve(A, b.unsqueeze(-1)))
+            err = float((torch.linalg.solve(A, b.unsqueeze(-1)).squeeze(-1) - x).abs().max())
+            bytes_ = batch * (8 * n * n + 8 * n + 8 * n + 4)
+            flops = batch * w_lu(n)
+            out[f"n{n}_batch{batch}"] = {"us": round(ms * 1e3, 2), "us_library": round(ms_lib * 1e3, 2),
+                                         "speedup": round(ms_lib / ms, 2), "max_abs_diff": err,
+                                         "GB_per_s": round(bytes_ / (ms * 1e-3) / 1e9, 1),
+                                         "TFLOP_per_s": round(flops / (ms * 1e-3) / 1e12, 3)}
+            log(f"bench: batched LU n={n} batch={batch}: {ms * 1e3:.1f} us vs library {ms_lib * 1e3:.1f} us")
+    out["note"] = ("roofline: hbm, peak 8000 GB/s (bytes per system 8n^2 + 16n + 4); flops W_LU(n) per system "
+                   "against the 157.3 TFLOP/s FP32 vector peak")
+    return out
+
+
 def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="mixed"):
     """Open-loop Poisson arrivals at `rate` requests/s into the serving loop.
     Mix: 40% one dense n = 8 system with 256 paths (the throughput workload's
@@ -321,7 +367,7 @@ def main():
     ap.add_argument("--trifocal-instances", type=int, default=1024,
                     help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
-                    help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,serving")
+                    help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,lu,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -438,6 +484,9 @@ def main():
         extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1, n_inst=args.trifocal_instances,
                                           n_inst_mixed=min(128, args.trifocal_instances))
         ctx.set_profiling(False)
+    if not args.no_extras and "lu" not in skip:
+        log("bench: standalone batched LU solves")
+        extras["batched_lu"] = lu_leg(ctx, hc, torch)
     if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
         extras["serving"] = serve_mix(ctx, hc)

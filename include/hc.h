@@ -243,6 +243,25 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
                           hc_c64 *endpoints, int32_t *status, hc_track_info *info,
                           void *stream);
 
+/* Batched complex linear solves A_k x_k = b_k, k < batch (section 6, "Linear
+ * System Solver": one fused kernel factors the augmented matrix [A_k | b_k] by
+ * LU with partial pivoting, which carries out the triangular solve with L on
+ * the way, and back-substitutes with the cached U).  The solver the path
+ * trackers use, on its own: one system per group of 4, 8, 16 or 32 lanes (the
+ * smallest >= n), one row per lane.
+ *   n:      1..32
+ *   fp32:   1: complex FP32 data and arithmetic (interleaved float pairs);
+ *           0: complex FP64 (hc_c64)
+ *   A:      [batch][n][n] row-major, element (i, j) of system k at k n^2 + i n + j
+ *   b, x:   [batch][n]; x may not alias A or b
+ *   info:   [batch] or NULL: 1 where a pivot is zero (x then holds inf/NaN), else 0
+ * Device pointers on the context's device; enqueued on `stream` (NULL = the null
+ * stream), outputs valid after it has been synchronised.  Allocates nothing.
+ * Errors: HC_E_INVALID (n outside 1..32, batch < 0, a NULL array with
+ * batch > 0), HC_E_DEVICE. */
+hc_status hc_solve_batched_device(hc_ctx *ctx, int32_t n, int64_t batch, int32_t fp32, const void *A,
+                                  const void *b, void *x, int32_t *info, void *stream);
+
 /* One job of a batch: a loaded system, its start points and instances, and its
  * output buffers, with the meaning and layout of the hc_track arguments.  All
  * pointers are device pointers. */

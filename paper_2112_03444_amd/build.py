@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libhc.so")
 SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp"),
            os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip"),
            os.path.join(CSRC, "hc_terms_q16.hip"), os.path.join(CSRC, "hc_terms_g16.hip"),
-           os.path.join(CSRC, "hc_terms_g20.hip")]
+           os.path.join(CSRC, "hc_terms_g20.hip"), os.path.join(CSRC, "hc_lu.hip")]
 ARCH = "gfx950"
 
 
@@ -33,6 +33,10 @@ def hipcc() -> str:
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fPIC"]
+# The 32-row group LU of the standalone solver is larger than the unroller's
+# default budget for #pragma unroll; rolled, its register rows would go to
+# scratch memory.
+EXTRA_FLAGS = {"hc_lu.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
 
 
 def build(verbose: bool = False) -> str:
@@ -43,7 +47,8 @@ def build(verbose: bool = False) -> str:
 
     with tempfile.TemporaryDirectory(prefix="hc_build_") as tmpdir:
         objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
-        cmds = [[hipcc(), *FLAGS, "-pthread", "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        cmds = [[hipcc(), *FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-pthread", "-I", INCLUDE, "-I", CSRC,
+                 "-c", src, "-o", obj]
                 for src, obj in zip(SOURCES, objs)]
         if verbose:
             for c in cmds:

@@ -725,6 +725,20 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
 
 extern "C" {
 
+hc_status hc_solve_batched_device(hc_ctx *c, int32_t n, int64_t batch, int32_t fp32, const void *A, const void *b,
+                                  void *x, int32_t *info, void *stream)
+{
+    clear_error();
+    if (!c) return fail(HC_E_INVALID, "hc_solve_batched_device: NULL context");
+    if (n < 1 || n > 32) return fail(HC_E_INVALID, "hc_solve_batched_device: n = %d outside 1..32", n);
+    if (batch < 0) return fail(HC_E_INVALID, "hc_solve_batched_device: batch = %lld", (long long)batch);
+    if (batch == 0) return HC_OK;
+    if (!A || !b || !x) return fail(HC_E_INVALID, "hc_solve_batched_device: NULL array");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(launch_lu_solve(n, batch, fp32 != 0, A, b, x, info, static_cast<hipStream_t>(stream)));
+    return HC_OK;
+}
+
 hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                           const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
                           const hc_c64 *gamma, const hc_opts *opts, hc_c64 *endpoints, int32_t *status,

@@ -184,6 +184,10 @@ int queue_waves_terms(int tk, bool fp32, bool param);
 hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st);
 hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long long max_total, hipStream_t st);
 
+// Standalone batched complex solves (hc_lu.hip): n <= 32, systems of one size.
+hipError_t launch_lu_solve(int n, long long batch, bool fp32, const void *A, const void *b, void *x, int *info,
+                           hipStream_t st);
+
 // Per-kind entry points (one source file per kind).
 template <int TK>
 hipError_t launch_track_terms_k(bool fp32, const TrackArgs &a, hipStream_t st);

@@ -126,6 +126,8 @@ def lib():
         L.hc_set_profiling.argtypes = [P, I32]
         L.hc_last_profile.restype = ctypes.c_int
         L.hc_last_profile.argtypes = [P, ctypes.POINTER(Profile)]
+        L.hc_solve_batched_device.restype = ctypes.c_int
+        L.hc_solve_batched_device.argtypes = [P, I32, I64, I32, P, P, P, P, P]
         L.hc_homogenize.restype = ctypes.c_int
         L.hc_homogenize.argtypes = [I32, I32, P, P, P, P, I32, I32, P]
         _lib = L
@@ -388,6 +390,29 @@ class Context:
                 if c_prev.dim() == 1:
                     c_prev = c_prev.expand(n_inst, -1).contiguous()
         return endpoints, status, info
+
+    def solve_batched_device(self, A, b, x, info=None, stream=None):
+        """hc_solve_batched_device on torch tensors: A [batch, n, n], b and x
+        [batch, n], all complex64 (FP32) or all complex128 (FP64), contiguous, on
+        the context's device; info [batch] int32 or None.  Enqueued on `stream`
+        (default: the current stream)."""
+        import torch
+        batch, n = A.shape[0], A.shape[1]
+        if A.shape != (batch, n, n) or b.shape != (batch, n) or x.shape != (batch, n):
+            raise ValueError("shapes: A [batch, n, n], b and x [batch, n]")
+        if not (A.dtype == b.dtype == x.dtype) or A.dtype not in (torch.complex64, torch.complex128):
+            raise ValueError("A, b, x must all be complex64 or all complex128")
+        if not (A.is_contiguous() and b.is_contiguous() and x.is_contiguous()):
+            raise ValueError("A, b, x must be contiguous")
+        if info is not None and (info.dtype != torch.int32 or info.shape != (batch,)):
+            raise ValueError("info must be int32 [batch]")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        fp32 = 1 if A.dtype == torch.complex64 else 0
+        _check(lib().hc_solve_batched_device(self.handle, n, batch, fp32, ctypes.c_void_p(A.data_ptr()),
+                                             ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                             None if info is None else ctypes.c_void_p(info.data_ptr()),
+                                             ctypes.c_void_p(stream.cuda_stream)))
 
     def track_batch_device(self, jobs, opts: Optional[Opts] = None, stream=None):
         """hc_track_batch_device.  jobs: list of dicts with keys sys (System),
