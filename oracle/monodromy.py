@@ -169,6 +169,18 @@ def check(system, c0, sols):
 
 
 TRIFOCAL_LOOPS = 19
+# Roots of the trifocal family closer than this (relative) are one root: FP64
+# refinement of its worst-conditioned roots (condition numbers up to 1e13)
+# leaves copies ~1e-8 apart, while distinct roots are >= 1e-4 apart.
+TRIFOCAL_MERGE_TOL = 1e-6
+
+
+def _save_trifocal(TF, S, p0, sols):
+    eta, d = check(S, TF.coefficients(p0), sols)
+    print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
+    out = TF.START_FILE
+    np.savez(out, params0=p0, coef0=TF.coefficients(p0), solutions=sols)
+    print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
 
 
 def main(argv):
@@ -179,11 +191,14 @@ def main(argv):
         # the run's tail finds a few new solutions every few loops; it is cut at
         # TRIFOCAL_LOOPS loops, so the stored set is not certified complete
         p0, sols = monodromy_family(TF.Family, seed=4, stall=5, max_loops=TRIFOCAL_LOOPS)
-        eta, d = check(S, TF.coefficients(p0), sols)
-        print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
-        out = TF.START_FILE
-        np.savez(out, params0=p0, coef0=TF.coefficients(p0), solutions=sols)
-        print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
+        _save_trifocal(TF, S, p0, distinct_rows(sols, tol=TRIFOCAL_MERGE_TOL))
+        return
+    if name == "trifocal-consolidate":
+        # the last step of the `trifocal` run alone, on a set stored before it
+        # existed: the result is the file a full run writes
+        import hc_inputs.trifocal as TF
+        z = np.load(TF.START_FILE)
+        _save_trifocal(TF, TF.trifocal_system(), z["params0"], distinct_rows(z["solutions"], tol=TRIFOCAL_MERGE_TOL))
         return
     if name != "triang4":
         raise SystemExit(f"unknown family {name}")

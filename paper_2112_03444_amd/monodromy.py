@@ -72,18 +72,20 @@ class LinearFamily:
 
 def distinct(sols: np.ndarray, tol: float = 1e-8) -> np.ndarray:
     """Rows of sols with near-duplicates (relative inf-norm distance <= tol,
-    relative to the larger row) removed, the first of equal rows kept.  Rows are
-    keyed by a fixed random real projection; two rows within tol of each other
-    have keys within 2 |w|_1 tol max|x|, so each row is compared only with the
-    earlier rows inside that window of the sorted keys."""
+    relative to the larger row) removed, the first of equal rows kept.  Rows
+    are keyed by a fixed random real projection of the row scaled by
+    s = max(1, |x|_inf); two rows within tol of each other differ by at most
+    2 tol after scaling, so their keys by at most 4 |w|_1 tol, and each row is
+    compared only with the earlier rows inside that window of the sorted keys."""
     sols = np.asarray(sols)
     n_rows = len(sols)
     if n_rows <= 1:
         return sols
     w = np.random.default_rng(12345).standard_normal(sols.shape[1])
-    key = (sols @ w).real + (sols @ w[::-1]).imag
     scale = np.maximum(1.0, np.max(np.abs(sols), axis=1))
-    reach = 2.0 * np.abs(w).sum() * tol * scale.max() * (1.0 + 1e-12)
+    y = sols / scale[:, None]
+    key = (y @ w).real + (y @ w[::-1]).imag
+    reach = 4.0 * np.abs(w).sum() * tol * (1.0 + 1e-9)
     order = np.argsort(key, kind="stable")
     ks = key[order]
     keep = np.zeros(n_rows, bool)
@@ -99,13 +101,13 @@ def distinct(sols: np.ndarray, tol: float = 1e-8) -> np.ndarray:
     return sols[keep]
 
 
-def _close(sols, orbit):
+def _close(sols, orbit, tol):
     if orbit is None or len(sols) == 0:
         return sols
     imgs = orbit(sols)
     if imgs is None:
         return sols
-    return distinct(np.concatenate([sols, np.asarray(imgs).reshape(-1, sols.shape[1])]))
+    return distinct(np.concatenate([sols, np.asarray(imgs).reshape(-1, sols.shape[1])]), tol)
 
 
 def _path(ctx, handle, family, p_from, p_to, sols, opts):
@@ -119,15 +121,16 @@ def _path(ctx, handle, family, p_from, p_to, sols, opts):
 
 
 def monodromy(ctx, family, seed: int = 0, stall: int = 10, max_loops: int = 500, target: Optional[int] = None,
-              precision: str = "fp64", log=None):
+              precision: str = "fp64", tol: float = 1e-6, log=None):
     """(p0, solutions [N, n]) of a generic member of `family` by monodromy loops
-    on the GPU (`ctx`: a Context)."""
+    on the GPU (`ctx`: a Context).  Endpoints closer than tol (relative) are one
+    root: refinement of badly conditioned roots leaves copies ~1e-8 apart."""
     system = family.system()
     handle = ctx.load_system(system, kind=_hc.HC_PARAMETER)
     opts = _hc.default_opts(precision=precision)
     rng = np.random.default_rng(seed)
     p0, x0 = family.fabricate(rng)
-    sols = _close(np.asarray(x0)[None, :], family.orbit)
+    sols = _close(np.asarray(x0)[None, :], family.orbit, tol)
     quiet = 0
     t0 = time.time()
     try:
@@ -136,7 +139,7 @@ def monodromy(ctx, family, seed: int = 0, stall: int = 10, max_loops: int = 500,
             xa = _path(ctx, handle, family, p0, pa, sols, opts)
             xb = _path(ctx, handle, family, pa, pb, xa, opts)
             back = _path(ctx, handle, family, pb, p0, xb, opts)
-            merged = _close(distinct(np.concatenate([sols, back])), family.orbit) if len(back) else sols
+            merged = _close(distinct(np.concatenate([sols, back]), tol), family.orbit, tol) if len(back) else sols
             grew = len(merged) - len(sols)
             sols = merged
             quiet = 0 if grew > 0 else quiet + 1

@@ -79,22 +79,27 @@ def forward_error_bound(S, c1, c0, x):
 
 def check_parity_conditioned(ep_g, st_g, ep_o, st_o, S, c1, c0, hc, rel=REL, slack=100.0):
     """check_parity with each oracle root's own tolerance max(rel, slack x its
-    forward-error bound): equal finite counts, one-to-one nearest matching.  For
-    well-conditioned roots the bound is far below rel and the bar is rel; badly
-    conditioned ones (near-degenerate scenes) cannot agree to rel between two
-    correct FP64 refinements."""
+    forward-error bound): equal finite counts, and the nearest GPU root of every
+    oracle root (a k-d tree in the real and imaginary parts, max-norm) is a
+    one-to-one pairing within that tolerance.  For well-conditioned roots the
+    bound is far below rel and the bar is rel; badly conditioned ones
+    (near-degenerate scenes) cannot agree to rel between two correct FP64
+    refinements."""
+    from scipy.spatial import cKDTree
     fg = ep_g[st_g == hc.HC_T_SUCCESS]
     fo = ep_o[st_o == oracle.SUCCESS]
     assert len(fg) == len(fo), (np.bincount(st_g, minlength=7), np.bincount(st_o, minlength=7))
-    left = list(range(len(fg)))
+    if len(fo) == 0:
+        return 0
+    emb = lambda z: np.concatenate([z.real, z.imag], axis=1)  # noqa: E731
+    _, j = cKDTree(emb(fg)).query(emb(fo), k=1, p=np.inf)
+    assert len(np.unique(j)) == len(j), "nearest-root pairing is not one-to-one"
+    d = np.max(np.abs(fg[j] - fo), axis=1) / np.maximum(1.0, np.max(np.abs(fo), axis=1))
     n_wide = 0
-    for q in fo:
-        d = [np.max(np.abs(fg[j] - q)) / max(1.0, np.max(np.abs(q))) for j in left]
-        k = int(np.argmin(d))
-        tol = max(rel, slack * forward_error_bound(S, c1, c0, q))
-        n_wide += tol > rel
-        assert d[k] <= tol, (d[k], tol)
-        left.pop(k)
+    for k in np.flatnonzero(d > rel):
+        tol = slack * forward_error_bound(S, c1, c0, fo[k])
+        n_wide += 1
+        assert d[k] <= tol, (k, d[k], tol)
     return n_wide
 
 
@@ -197,9 +202,10 @@ def batch(trifocal):
 
 
 def test_trifocal_full_batch_sampled(hc, ctx, trifocal, batch):
-    """The 1024-instance batch in mixed mode on device buffers, as the benchmark
-    runs it: every finite endpoint's residual, and the sampled instances against
-    the oracle."""
+    """The 1024-instance batch in FP64 on device buffers, as the benchmark runs
+    it: every finite endpoint's residual, and the sampled instances against the
+    oracle (mixed mode is checked on the sampled instances through the
+    host-buffer entry point)."""
     import torch
     S, p0, sols, ps = trifocal
     c0, mids, ends, oe, os_ = batch
@@ -210,7 +216,7 @@ def test_trifocal_full_batch_sampled(hc, ctx, trifocal, batch):
     st = torch.empty((n_inst, N), dtype=torch.int32, device=dev)
     inf = torch.empty((n_inst, N, 32), dtype=torch.uint8, device=dev)
     ctx.track_piecewise_device(ps, wp, torch.from_numpy(sols).to(dev), ep, st, inf,
-                               opts=hc.default_opts(precision="mixed"))
+                               opts=hc.default_opts(precision="fp64"))
     torch.cuda.synchronize()
     ep, st = ep.cpu().numpy(), st.cpu().numpy()
     info = inf.cpu().numpy().view(hc.INFO_DTYPE)[..., 0]

@@ -113,14 +113,21 @@ def test_start_set_is_regular_distinct_and_sign_closed(start):
     """The stored monodromy set: every point a root of the start instance with
     tiny backward error, pairwise distinct, and closed under the eight-element
     symmetry group (so its size is a multiple of 8)."""
+    from scipy.spatial import cKDTree
     S = TF.trifocal_system()
     p0, sols = start
     c0 = TF.coefficients(p0)
     assert sols.shape[1] == 18 and len(sols) % 8 == 0
     assert max(oracle.residual(S, c0, x) for x in sols) < 1e-12
-    assert len(M.distinct_rows(sols)) == len(sols)
-    orbit = TF.symmetry_orbit(sols).reshape(-1, 18)
-    assert len(M.distinct_rows(np.concatenate([sols, orbit]))) == len(sols)
+    # max-norm distances over real and imaginary parts, relative to max(1, |x|)
+    emb = lambda z: np.concatenate([z.real, z.imag], axis=-1)  # noqa: E731
+    scale = np.maximum(1.0, np.max(np.abs(sols), axis=1))
+    tree = cKDTree(emb(sols))
+    d2, _ = tree.query(emb(sols), k=2, p=np.inf)      # nearest other solution
+    assert np.all(d2[:, 1] / scale > 1e-6)
+    for img in TF.symmetry_orbit(sols):               # every image is a stored solution
+        d, j = tree.query(emb(img), k=1, p=np.inf)
+        assert np.all(d / scale[j] <= 1e-12)
 
 
 def test_noise_free_ground_truth_is_among_the_oracle_endpoints(start):
