@@ -1130,7 +1130,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     std::vector<RefineArgs> refs[kRefSlots];  // [n] dense, [kMaxN + 1 + kind] term lists
     std::vector<DedupArgs> dedups;
     std::vector<InitArgs> retracks;
-    long long ref_items[kRefSlots] = {};
+    long long ref_items[kRefSlots] = {}, ref_total[kRefSlots] = {};
     int max_inst = 0;
     for (int k = 0; k < n_jobs; k++) {
         const Plan &p = plan[k];
@@ -1158,6 +1158,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         refs[rk].push_back(ra);
         ref_items[rk] = std::max(ref_items[rk], rk > kMaxN ? p.total
                                                                 : (long long)p.j->n_inst * ((p.j->n_start + 63) / 64));
+        ref_total[rk] = std::max(ref_total[rk], p.total);
         DedupArgs da;
         da.n = p.n;
         da.n_start = p.j->n_start;
@@ -1233,7 +1234,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
             if (rk > kMaxN)
                 HIP_TRY(launch_refine_terms_many(rk - kMaxN - 1, d, (int)refs[rk].size(), ref_items[rk], st));
             else
-                HIP_TRY(launch_refine_many(rk, d, (int)refs[rk].size(), ref_items[rk], st));
+                HIP_TRY(launch_refine_many(rk, d, (int)refs[rk].size(), ref_items[rk], ref_total[rk], st));
         }
         return HC_OK;
     };

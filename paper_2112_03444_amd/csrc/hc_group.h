@@ -354,6 +354,21 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+// NaN-propagating maximum over the G lanes of a group (butterflies as in
+// group_sum), identical in every lane.
+__device__ __forceinline__ double dmax_pick(double v, double o) { return (o > v || isnan(o)) ? o : v; }
+
+template <int G>
+__device__ __forceinline__ double group_max_d(double v)
+{
+    v = dmax_pick(v, dpp<0xB1>(v));
+    v = dmax_pick(v, dpp<0x4E>(v));
+    if (G >= 8) v = dmax_pick(v, dpp<0x141>(v));
+    if (G >= 16) v = dmax_pick(v, dpp<0x140>(v));
+    if (G >= 32) v = dmax_pick(v, swz_xor16(v));
+    return v;
+}
+
 // True in every lane of the group if p holds in any of its lanes.
 template <int G>
 __device__ __forceinline__ bool group_any(bool p, int base)

@@ -171,6 +171,10 @@ hipError_t launch_fill_u32(unsigned *p, unsigned value, int count, hipStream_t s
 // (which must be zero at launch).
 hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, hipStream_t st);
 int group_lanes(int n);
+// FP64 refinement of dense systems with 2 <= n <= 8 in the group layout: one job
+// (many = false, *a read on the host) or count jobs (a in device memory);
+// max_total = the largest path count of the jobs.
+hipError_t launch_refine_group(int n, const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st);
 
 // Term-list layout (hc_terms_impl.h): kind tk = 0 (degree <= 2, n <= 16),
 // 1 (any degree <= 8, n <= 16) or 2 (any degree <= 8, n <= 20); 16 lanes per
@@ -204,6 +208,9 @@ hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
 hipError_t launch_prep_many(const PrepArgs *a, int count, long long max_work, hipStream_t st);
 hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, hipStream_t st);
 hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, hipStream_t st);
-hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, hipStream_t st);
+// max_items: the largest n_inst * ceil(n_start / 64) of the jobs (n = 1), max_total
+// the largest path count (2 <= n <= 8)
+hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, long long max_total,
+                              hipStream_t st);
 
 }  // namespace hcx

@@ -784,37 +784,22 @@ static hipError_t launch_refine_many_n(const RefineArgs *a, int count, long long
     return hipGetLastError();
 }
 
-// max_items: the largest n_inst * ceil(n_start / 64) of the jobs
-hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, hipStream_t st)
+// One path per lane for n = 1; 2 <= n <= 8 refine in the group layout
+// (hc_track_group.hip), whose registers hold one row per lane instead of the
+// whole n x (n + 1) system.
+hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, long long max_total,
+                              hipStream_t st)
 {
     if (count == 0 || max_items == 0) return hipSuccess;
-    switch (n) {
-    case 1: return launch_refine_many_n<1>(a, count, max_items, st);
-    case 2: return launch_refine_many_n<2>(a, count, max_items, st);
-    case 3: return launch_refine_many_n<3>(a, count, max_items, st);
-    case 4: return launch_refine_many_n<4>(a, count, max_items, st);
-    case 5: return launch_refine_many_n<5>(a, count, max_items, st);
-    case 6: return launch_refine_many_n<6>(a, count, max_items, st);
-    case 7: return launch_refine_many_n<7>(a, count, max_items, st);
-    case 8: return launch_refine_many_n<8>(a, count, max_items, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (n == 1) return launch_refine_many_n<1>(a, count, max_items, st);
+    return launch_refine_group(n, a, count, max_total, true, st);
 }
 
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st)
 {
     if (a.total == 0) return hipSuccess;
-    switch (n) {
-    case 1: return launch_refine_n<1>(a, st);
-    case 2: return launch_refine_n<2>(a, st);
-    case 3: return launch_refine_n<3>(a, st);
-    case 4: return launch_refine_n<4>(a, st);
-    case 5: return launch_refine_n<5>(a, st);
-    case 6: return launch_refine_n<6>(a, st);
-    case 7: return launch_refine_n<7>(a, st);
-    case 8: return launch_refine_n<8>(a, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (n == 1) return launch_refine_n<1>(a, st);
+    return launch_refine_group(n, &a, 1, a.total, false, st);
 }
 
 }  // namespace hcx

@@ -23,21 +23,6 @@ constexpr size_t terms_wave_bytes()
     return (size_t)terms_lds_cx<TermCfg<TK>::NM, TermCfg<TK>::G>() * sizeof(cx<double>);
 }
 
-// NaN-propagating maximum over the G lanes of a group (butterflies as in
-// group_sum), identical in every lane.
-__device__ __forceinline__ double dmax_pick(double v, double o) { return (o > v || isnan(o)) ? o : v; }
-
-template <int G>
-__device__ __forceinline__ double group_max_d(double v)
-{
-    v = dmax_pick(v, dpp<0xB1>(v));
-    v = dmax_pick(v, dpp<0x4E>(v));
-    if (G >= 8) v = dmax_pick(v, dpp<0x141>(v));
-    if (G >= 16) v = dmax_pick(v, dpp<0x140>(v));
-    if (G >= 32) v = dmax_pick(v, swz_xor16(v));
-    return v;
-}
-
 }  // namespace
 
 // Persistent tracker for one job on the term-list layout.

@@ -158,4 +158,160 @@ hipError_t launch_track_group(int n, bool fp32, const TrackArgs &a, hipStream_t 
 
 int group_lanes(int n) { return n <= 4 ? 4 : 8; }
 
+// FP64 endpoint refinement and classification for the dense quadratic layout,
+// one path per group of G lanes (64 / G per wavefront) with the trackers' row
+// build and group solver: Newton on F at t = 1 (where H = F and H_x = F_x) until
+// the correction is below tau_refine (1 + |x|) or max_refine iterations, then the
+// relative backward error eta = max_i |F_i| / sum_k |c_ik| |m_k(x)| over the
+// equations (one per lane) and the final status.  The table is the kernel table
+// [inst][eq][term] in FP64, diagonal quadratic coefficients stored doubled.
+template <int N, int G>
+__device__ __forceinline__ void refine_grp_body(const RefineArgs &a, int block)
+{
+    constexpr int T = dense_terms(N), PW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & (G - 1);
+    const int base = lane - r;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (a.total == 0) return;
+    const long long gid = ((long long)block * 4 + wib) * PW + lane / G;
+    const bool valid = gid < a.total;
+    const long long g = valid ? gid : 0;  // spare groups redo path 0 and write nothing
+    const bool own = r < N;
+    const int rr = own ? r : 0;
+    const int inst = (int)(g / a.n_start);
+    const double *c1 = a.coef + ((size_t)inst * N + rr) * T * 2;
+    cx<double> gam = {1.0, 0.0};
+    if (a.gamma) gam = {a.gamma[2 * inst], a.gamma[2 * inst + 1]};
+    const bool d2 = own && ((a.deg2 >> r) & 1u);
+    const TrackState S = a.s;
+    const long long total = a.total;
+    int st = S.status[g];
+    const bool done = st == kDone;  // final from an earlier pass: nothing to write
+    cx<double> x = own ? cx<double>{S.xr[r * total + g], S.xi[r * total + g]} : cx<double>{0.0, 0.0};
+    bool act = valid && st == kReached;
+    int rits = 0;
+    for (int it = 0; it < a.max_refine; it++) {
+        if (ballot(act) == 0ull) break;
+        const double *p1 = c1;
+        asm volatile("" : "+v"(p1));
+        cx<double> d;
+        double nd;
+        const bool sing = stage_solve<N, G, double, false>(GlobalRow<double>{p1}, nullptr, p1, r, base, d2, gam, gam,
+                                                           x, 1.0, false, false, d, nd);
+        if (act) {
+            if (sing) {
+                st = HC_T_SINGULAR;
+                act = false;
+            } else {
+                x = {x.re + d.re, x.im + d.im};
+                const double nx = sqrt(group_sum<G>(abs2(x)));
+                rits++;
+                if (sqrt(nd) <= a.tau_refine * (1.0 + nx)) act = false;
+            }
+        }
+    }
+    // classification: the whole wavefront takes part in the group reductions
+    const bool nonfin = group_any<G>(own && !finite(x), base);
+    const double big = group_max_d<G>(abs2(x));
+    cx<double> xs[N];
+    gather<G, N>(x, xs);
+    // residual of the lane's equation: constant, linear and quadratic terms
+    cx<double> F = {c1[0], c1[1]};
+    double den = sqrt(abs2(F));
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const cx<double> L = {c1[2 * (1 + j)], c1[2 * (1 + j) + 1]};
+        F = cfma(L, xs[j], F);
+        den += sqrt(abs2(L)) * sqrt(abs2(xs[j]));
+    }
+    int q = 1 + N;
+#pragma unroll
+    for (int p = 0; p < N; p++) {
+#pragma unroll
+        for (int b = p; b < N; b++, q++) {
+            cx<double> cq = {c1[2 * q], c1[2 * q + 1]};
+            if (p == b) cq = {0.5 * cq.re, 0.5 * cq.im};
+            const cx<double> m = cmul(xs[p], xs[b]);
+            F = cfma(cq, m, F);
+            den += sqrt(abs2(cq)) * sqrt(abs2(m));
+        }
+        asm volatile("" ::: "memory");  // one row segment of the table in registers at a time
+    }
+    const double num = sqrt(abs2(F));
+    const double e = !own ? 0.0 : den > 0.0 ? num / den : (num == 0.0 ? 0.0 : INFINITY);
+    const double resid = group_max_d<G>(e);
+    if (!valid || done) return;
+    double res_out = NAN;
+    if (st == kReached) {
+        if (nonfin) {
+            st = HC_T_NONFINITE;
+        } else {
+            res_out = resid;
+            if (big > a.inf2)
+                st = HC_T_AT_INFINITY;
+            else if (!(resid <= a.eta_max))
+                st = HC_T_REFINE_FAILED;
+            else
+                st = HC_T_SUCCESS;
+        }
+    } else if (st < 0) {
+        st = HC_T_MAX_STEPS;  // unreachable after a full run: every path ends
+    }
+    if (own) {
+        a.endpoints[(g * N + r) * 2] = x.re;
+        a.endpoints[(g * N + r) * 2 + 1] = x.im;
+    }
+    if (r == 0) {
+        a.status[g] = st;
+        if (a.info) {
+            hc_track_info inf;
+            inf.steps = S.steps[g];
+            inf.rejects = S.rejects[g];
+            inf.newton_its = S.nits[g];
+            inf.refine_its = rits;
+            inf.escalated = S.escal[g] != 0 ? 1 : 0;
+            inf.reserved = 0;
+            inf.residual = res_out;
+            a.info[g] = inf;
+        }
+    }
+}
+
+template <int N, int G>
+__global__ __launch_bounds__(256, 2) void k_refine_grp(const RefineArgs a) { refine_grp_body<N, G>(a, blockIdx.x); }
+
+template <int N, int G>
+__global__ __launch_bounds__(256, 2) void k_refine_grp_many(const RefineArgs *a)
+{
+    refine_grp_body<N, G>(a[blockIdx.y], blockIdx.x);
+}
+
+template <int N, int G>
+static hipError_t launch_refine_grp(const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st)
+{
+    constexpr int PB = 4 * (64 / G);  // paths per block
+    const unsigned blocks = (unsigned)((max_total + PB - 1) / PB);
+    if (many)
+        hipLaunchKernelGGL((k_refine_grp_many<N, G>), dim3(blocks, (unsigned)count), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_refine_grp<N, G>), dim3(blocks), dim3(256), 0, st, *a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_group(int n, const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st)
+{
+    if (count == 0 || max_total == 0) return hipSuccess;
+    switch (n) {
+    case 2: return launch_refine_grp<2, 4>(a, count, max_total, many, st);
+    case 3: return launch_refine_grp<3, 4>(a, count, max_total, many, st);
+    case 4: return launch_refine_grp<4, 4>(a, count, max_total, many, st);
+    case 5: return launch_refine_grp<5, 8>(a, count, max_total, many, st);
+    case 6: return launch_refine_grp<6, 8>(a, count, max_total, many, st);
+    case 7: return launch_refine_grp<7, 8>(a, count, max_total, many, st);
+    case 8: return launch_refine_grp<8, 8>(a, count, max_total, many, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace hcx
