@@ -188,6 +188,9 @@ __device__ __forceinline__ void refine_grp_body(const RefineArgs &a, int block)
     const long long total = a.total;
     int st = S.status[g];
     const bool done = st == kDone;  // final from an earlier pass: nothing to write
+    // a wavefront with nothing to write (the re-refinement after a crossing
+    // check: all but the re-tracked paths are done) leaves at once
+    if (ballot(valid && !done) == 0ull) return;
     cx<double> x = own ? cx<double>{S.xr[r * total + g], S.xi[r * total + g]} : cx<double>{0.0, 0.0};
     bool act = valid && st == kReached;
     int rits = 0;
