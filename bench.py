@@ -367,7 +367,7 @@ def main():
     ap.add_argument("--trifocal-instances", type=int, default=1024,
                     help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
-                    help="comma-separated legs to skip: per_instance,latency,triangulation,trifocal,lu,serving")
+                    help="comma-separated legs to skip: per_instance,host,latency,triangulation,trifocal,lu,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -434,6 +434,23 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         extras["per_instance_fp64"] = {"tracks_per_s": n_inst * n_start / dt, "ms_per_instance": dt / n_inst * 1e3}
+    if not args.no_extras and "host" not in skip:
+        # the host-buffer entry point on the same batch: coefficients and gammas
+        # copied in, endpoints, status and info copied out over PCIe in each call
+        log("bench: host-buffer entry point (mixed, copies included)")
+        om = hc.default_opts(precision="mixed")
+        ctx.set_profiling(False)
+        ctx.track(sysh, coef, gam, opts=om)
+        ts = []
+        for _ in range(max(1, args.steps)):
+            t0 = time.perf_counter()
+            ctx.track(sysh, coef, gam, opts=om)
+            ts.append(time.perf_counter() - t0)
+        dt = float(np.mean(ts))
+        extras["host_buffers_mixed"] = {"tracks_per_s": n_inst * n_start / dt, "ms_per_step": dt * 1e3,
+                                        "bytes_in": int(coef.nbytes + gam.nbytes),
+                                        "bytes_out": int(n_inst * n_start * (n * 16 + 4 + 32))}
+        log(f"bench: host buffers: {dt * 1e3:.2f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
     if not args.no_extras and "latency" not in skip:
         o64 = hc.default_opts(precision="fp64")
         ctx.set_profiling(False)
