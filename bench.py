@@ -420,6 +420,10 @@ def main():
         log(f"bench: {mode}: {dt * 1e3:.2f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
 
     extras = {}
+    # the vector FMA rates the ALU roofline's peaks stand for, measured on this device
+    extras["measured_peak_tflops"] = {"fp32_plain": round(ctx.measure_vector_peak(False), 2),
+                                      "fp64": round(ctx.measure_vector_peak(True), 2)}
+    log(f"bench: measured vector FMA peaks (TFLOP/s): {extras['measured_peak_tflops']}")
     skip = set(x for x in args.skip.split(",") if x)
     if not args.no_extras and "per_instance" not in skip:
         # paper-style comparator: plain FP64, one instance per call (one launch set each)

@@ -262,6 +262,15 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
 hc_status hc_solve_batched_device(hc_ctx *ctx, int32_t n, int64_t batch, int32_t fp32, const void *A,
                                   const void *b, void *x, int32_t *info, void *stream);
 
+/* Diagnostic: the measured vector FMA rate of the context's device in TFLOP/s
+ * (2 FLOP per FMA), the check of the peak the trackers' ALU roofline is quoted
+ * against.  Every lane of 8 wavefronts per SIMD runs 16 independent FMA chains
+ * on registers; fp64 = 1 times FP64 FMAs, fp64 = 0 plain FP32 FMAs (one value
+ * per lane and instruction, as in the trackers: the library is built without
+ * packed FP32).  Synchronous on the null stream; allocates and frees ~4 MB of
+ * device memory.  Errors: HC_E_INVALID (NULL ctx or tflops), HC_E_DEVICE. */
+hc_status hc_measure_vector_peak(hc_ctx *ctx, int32_t fp64, double *tflops);
+
 /* One job of a batch: a loaded system, its start points and instances, and its
  * output buffers, with the meaning and layout of the hc_track arguments.  All
  * pointers are device pointers. */

@@ -739,6 +739,17 @@ hc_status hc_solve_batched_device(hc_ctx *c, int32_t n, int64_t batch, int32_t f
     return HC_OK;
 }
 
+hc_status hc_measure_vector_peak(hc_ctx *c, int32_t fp64, double *tflops)
+{
+    clear_error();
+    if (!c || !tflops) return fail(HC_E_INVALID, "hc_measure_vector_peak: NULL argument");
+    HIP_TRY(hipSetDevice(c->device));
+    double v = 0.0;
+    HIP_TRY(measure_peak_fma(fp64 != 0, &v, nullptr));
+    *tflops = v;
+    return HC_OK;
+}
+
 hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                           const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
                           const hc_c64 *gamma, const hc_opts *opts, hc_c64 *endpoints, int32_t *status,

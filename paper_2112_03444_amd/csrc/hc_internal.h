@@ -188,6 +188,9 @@ int queue_waves_terms(int tk, bool fp32, bool param);
 hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st);
 hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long long max_total, hipStream_t st);
 
+// Measured vector FMA rate (hc_peak.hip), TFLOP/s.
+hipError_t measure_peak_fma(bool fp64, double *tflops, hipStream_t st);
+
 // Standalone batched complex solves (hc_lu.hip): n <= 32, systems of one size.
 hipError_t launch_lu_solve(int n, long long batch, bool fp32, const void *A, const void *b, void *x, int *info,
                            hipStream_t st);

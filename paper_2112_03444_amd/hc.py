@@ -128,6 +128,8 @@ def lib():
         L.hc_last_profile.argtypes = [P, ctypes.POINTER(Profile)]
         L.hc_solve_batched_device.restype = ctypes.c_int
         L.hc_solve_batched_device.argtypes = [P, I32, I64, I32, P, P, P, P, P]
+        L.hc_measure_vector_peak.restype = ctypes.c_int
+        L.hc_measure_vector_peak.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
         L.hc_homogenize.restype = ctypes.c_int
         L.hc_homogenize.argtypes = [I32, I32, P, P, P, P, I32, I32, P]
         _lib = L
@@ -413,6 +415,13 @@ class Context:
                                              ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                              None if info is None else ctypes.c_void_p(info.data_ptr()),
                                              ctypes.c_void_p(stream.cuda_stream)))
+
+    def measure_vector_peak(self, fp64: bool) -> float:
+        """hc_measure_vector_peak: the device's measured FMA rate in TFLOP/s
+        (FP64, or plain one-value-per-lane FP32)."""
+        v = ctypes.c_double(0.0)
+        _check(lib().hc_measure_vector_peak(self.handle, 1 if fp64 else 0, ctypes.byref(v)))
+        return v.value
 
     def track_batch_device(self, jobs, opts: Optional[Opts] = None, stream=None):
         """hc_track_batch_device.  jobs: list of dicts with keys sys (System),
