@@ -21,10 +21,11 @@ such as products of image coordinates) loop in parameter space instead; each
 segment follows the family's waypoints so that every leg is a linear
 coefficient homotopy that stays inside the family (`monodromy_family`).
 
-Usage (writes tests/golden/start_triang4.npz or start_trifocal.npz and prints
-its sha256):
+Usage (writes tests/golden/start_triang4.npz, start_triang3.npz or
+start_trifocal.npz and prints its sha256):
 
     python -m oracle.monodromy triang4
+    python -m oracle.monodromy triang3
     python -m oracle.monodromy trifocal
 """
 from __future__ import annotations
@@ -200,14 +201,15 @@ def main(argv):
         z = np.load(TF.START_FILE)
         _save_trifocal(TF, TF.trifocal_system(), z["params0"], distinct_rows(z["solutions"], tol=TRIFOCAL_MERGE_TOL))
         return
-    if name != "triang4":
+    if name not in ("triang4", "triang3"):
         raise SystemExit(f"unknown family {name}")
     import hc_inputs.vision as V
-    S = V.triangulation_system()
+    n_views = int(name[-1])
+    S = V.triangulation_system(n_views)
     c0, sols = monodromy(S, seed=4)
     eta, d = check(S, c0, sols)
     print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
-    out = os.path.join(ROOT, "tests", "golden", "start_triang4.npz")
+    out = os.path.join(ROOT, "tests", "golden", f"start_triang{n_views}.npz")
     np.savez(out, coef0=c0, solutions=sols)
     print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
 
