@@ -135,14 +135,15 @@ def cpu_baseline(S, coef, gam, budget_s=12.0):
                       f"{threads} threads; success {np.mean(ost == 0):.4f}"}
 
 
-def vision_leg(ctx, hc, torch, steps, warmup):
-    """4-view triangulation batch (4096 instances x 296 paths, parameter homotopy
-    from the monodromy start set) in both precisions."""
+def vision_leg(ctx, hc, torch, steps, warmup, n_views=4):
+    """N-view triangulation batch (4096 instances; 4 views: 296 paths each, 3
+    views: 94; parameter homotopy from the monodromy start set) in both
+    precisions."""
     import hc_inputs.vision as V
     dev = torch.device("cuda:0")
-    S = V.triangulation_system()
-    c0, sols = V.start_instance()
-    _, coef, _ = V.vision_workload("triang4_batch4096")
+    S = V.triangulation_system(n_views)
+    c0, sols = V.start_instance(n_views)
+    _, coef, _ = V.vision_workload(f"triang{n_views}_batch4096")
     n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
     p = torch.from_numpy(coef).to(dev)
     ps = torch.from_numpy(c0).to(dev)
@@ -152,8 +153,9 @@ def vision_leg(ctx, hc, torch, steps, warmup):
     info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
     sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
     wst = w_eval_terms(S, True) + w_lu(n)
-    out = {"workload": "triang4_batch4096: 4096 noisy 4-view triangulation instances (n=14, 134 terms), "
-                       "parameter homotopy from a 296-solution monodromy start set (1,212,416 paths)"}
+    out = {"workload": f"triang{n_views}_batch4096: {n_inst} noisy {n_views}-view triangulation instances "
+                       f"(n={n}, {S.n_terms} terms), parameter homotopy from a {n_start}-solution monodromy "
+                       f"start set ({n_inst * n_start:,} paths)"}
     for mode in ("fp64", "mixed"):
         opts = hc.default_opts(precision=mode)
         for _ in range(warmup):
@@ -176,7 +178,8 @@ def vision_leg(ctx, hc, torch, steps, warmup):
                      "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
                      "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
                                           f"k_track_terms<0,{'float' if mode == 'mixed' else 'double'},true>")}
-        log(f"bench: triangulation {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
+        log(f"bench: {n_views}-view triangulation {mode}: {dt * 1e3:.1f} ms/step, "
+            f"{n_inst * n_start / dt:.3e} tracks/s")
     out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
     return out
 
@@ -367,7 +370,8 @@ def main():
     ap.add_argument("--trifocal-instances", type=int, default=1024,
                     help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
-                    help="comma-separated legs to skip: per_instance,host,latency,triangulation,trifocal,lu,serving")
+                    help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,trifocal,lu,"
+                         "serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -498,6 +502,11 @@ def main():
         log("bench: 4-view triangulation batch")
         ctx.set_profiling(True)
         extras["triangulation"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
+        ctx.set_profiling(False)
+    if not args.no_extras and "triangulation3" not in skip:
+        log("bench: 3-view triangulation batch")
+        ctx.set_profiling(True)
+        extras["triangulation3"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1, n_views=3)
         ctx.set_profiling(False)
     if not args.no_extras and "trifocal" not in skip:
         log("bench: trifocal pose batch")

@@ -164,6 +164,55 @@ def test_triangulation_full_batch_sampled(hc, ctx, triang):
         check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
 
 
+@pytest.fixture(scope="module")
+def triang3(hc, ctx):
+    S = V.triangulation_system(3)
+    c0, sols = V.start_instance(3)
+    ps = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    return S, c0, sols, ps
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_triangulation3_parity(hc, ctx, triang3, precision):
+    """3-view triangulation (n = 9) from its 94-solution monodromy start set to
+    4 scenes.  FP64: set parity.  Mixed: ~6% of these paths head for infinity
+    or an ill-conditioned root and end at the minimum step; which of them do
+    depends on the FP32 part of the path, so the comparison is path by path
+    (check_paths_where_both_succeed, at most 2 of the 94 paths disagreeing)."""
+    S, c0, sols, ps = triang3
+    _, coef, _ = V.triangulation_instances(4, seed=5600, n_views=3)
+    ep, st, info = ctx.track(ps, coef, start=sols, p_start=c0, opts=hc.default_opts(precision=precision))
+    oep, ost, _ = oracle.track(S, coef, start=sols, coef0=c0, kind=oracle.LINEAR)
+    for i in range(4):
+        if precision == "fp64":
+            check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
+        else:
+            check_paths_where_both_succeed(ep[i], st[i], info["residual"][i], oep[i], ost[i], hc,
+                                           max_frac=2.5 / 94)
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
+
+
+def test_triangulation3_full_batch_sampled(hc, ctx, triang3):
+    """The 4096-instance 3-view batch (385,024 paths) in mixed mode, as the
+    benchmark runs it; sampled instances against the oracle, every finite
+    endpoint's residual, distinctness on a sample."""
+    S, c0, sols, ps = triang3
+    _, coef, _ = V.vision_workload("triang3_batch4096")
+    ep, st, info = ctx.track(ps, coef, start=sols, p_start=c0, opts=hc.default_opts(precision="mixed"))
+    assert ep.shape == (4096, 94, 9)
+    ok = st == hc.HC_T_SUCCESS
+    assert np.all(info["residual"][ok] <= 1e-10)
+    assert ok.sum(axis=1).min() >= 60
+    for i in range(0, 4096, 512):
+        f = ep[i][ok[i]]
+        d = np.abs(f[:, None, :] - f[None, :, :]).max(-1) + np.eye(len(f)) * 1e9
+        assert d.min() > 1e-6
+    sample = [0, 2047, 4095]
+    oep, ost, _ = oracle.track(S, coef[sample], start=sols, coef0=c0, kind=oracle.LINEAR)
+    for k, i in enumerate(sample):
+        check_instance_parity(ep[i], st[i], oep[k], ost[k], hc)
+
+
 def test_terms_chunked_launches_equal_one_shot(hc, ctx, triang):
     S, c0, sols, ps = triang
     _, coef, _ = V.triangulation_instances(2, seed=5300)
