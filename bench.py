@@ -184,6 +184,36 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4):
     return out
 
 
+def p3p_leg(ctx, hc, torch, steps, warmup):
+    """P3P batch (65536 noisy instances x 8 total-degree paths, dense tables with
+    n = 3) in both precisions, on device buffers."""
+    import hc_inputs.p3p as P
+    dev = torch.device("cuda:0")
+    S, coef, gam, _ = P.p3p_workload("p3p_batch65536")
+    n_inst, n_start, n = coef.shape[0], 8, S.n
+    p = torch.from_numpy(coef).to(dev)
+    g = torch.from_numpy(gam).to(dev)
+    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    sysh = ctx.load_system(S)
+    wst = w_eval_terms(S, False) + w_lu(n)
+    out = {"workload": f"p3p_batch65536: {n_inst} noisy P3P instances (3 quadratics in the depths, 13 terms), "
+                       f"total-degree homotopy, {n_inst * n_start:,} paths"}
+    for mode in ("fp64", "mixed"):
+        opts = hc.default_opts(precision=mode)
+        dt, profs = time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch)
+        stn = st.cpu().numpy()
+        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
+                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
+                                          f"k_track_grp<3,4,{'float' if mode == 'mixed' else 'double'},false>")}
+        log(f"bench: P3P {mode}: {dt * 1e3:.2f} ms/step, {n_inst / dt:.3e} solves/s")
+    ctx.free_system(sysh)
+    return out
+
+
 def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
     """Trifocal pose batch (instances of trifocal_batch1024, each solved from the
     monodromy start set along the family's two-leg parameter path) on device
@@ -370,8 +400,8 @@ def main():
     ap.add_argument("--trifocal-instances", type=int, default=1024,
                     help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
-                    help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,trifocal,lu,"
-                         "serving")
+                    help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,p3p,"
+                         "trifocal,lu,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -502,6 +532,11 @@ def main():
         log("bench: 4-view triangulation batch")
         ctx.set_profiling(True)
         extras["triangulation"] = vision_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
+        ctx.set_profiling(False)
+    if not args.no_extras and "p3p" not in skip:
+        log("bench: P3P batch")
+        ctx.set_profiling(True)
+        extras["p3p"] = p3p_leg(ctx, hc, torch, args.steps, 1)
         ctx.set_profiling(False)
     if not args.no_extras and "triangulation3" not in skip:
         log("bench: 3-view triangulation batch")
