@@ -1142,7 +1142,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     std::vector<DedupArgs> dedups;
     std::vector<InitArgs> retracks;
     long long ref_items[kRefSlots] = {}, ref_total[kRefSlots] = {};
-    int max_inst = 0;
+    int max_inst = 0, max_start = 0;
     for (int k = 0; k < n_jobs; k++) {
         const Plan &p = plan[k];
         if (p.total == 0) continue;
@@ -1181,6 +1181,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         da.s = ta.s;
         dedups.push_back(da);
         max_inst = std::max(max_inst, p.j->n_inst);
+        max_start = std::max(max_start, p.j->n_start);
         InitArgs ir = p.init;
         ir.retrack = 1;
         retracks.push_back(ir);
@@ -1261,7 +1262,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         // crossing check of every job, one FP64 pass over the queues, then the
         // refinement of the re-tracked paths
         HIP_TRY(launch_dedup_many(reinterpret_cast<const DedupArgs *>(qb + o_dedup), (int)dedups.size(), max_inst,
-                                  st));
+                                  max_start, st));
         HIP_TRY(launch_init_many(reinterpret_cast<const InitArgs *>(qb + o_retr), (int)retracks.size(), max_total,
                                  st));
         rc = run_pass(false);

@@ -210,7 +210,7 @@ hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
 // Batch API: one launch per step over many jobs (argument arrays in device memory).
 hipError_t launch_prep_many(const PrepArgs *a, int count, long long max_work, hipStream_t st);
 hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, hipStream_t st);
-hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, hipStream_t st);
+hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, int max_start, hipStream_t st);
 // max_items: the largest n_inst * ceil(n_start / 64) of the jobs (n = 1), max_total
 // the largest path count (2 <= n <= 8)
 hipError_t launch_refine_many(int n, const RefineArgs *a, int count, long long max_items, long long max_total,

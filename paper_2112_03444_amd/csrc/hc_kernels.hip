@@ -445,13 +445,22 @@ __global__ void k_init_many(const InitArgs *a)
 // have crossed (one jumped onto the other's path); both start over in FP64.
 // A complex projection of every SUCCESS endpoint is kept in LDS and compared
 // first; candidates are then compared in full.
+template <int C>
+struct k_dedup_tag {
+    static constexpr int cap = C;
+};
+
+// CAP: LDS entries of the block (the launcher picks the smallest of 64, 1024 and
+// kDedupMax that holds every instance it covers, so small instances do not tie
+// up 128 KB of LDS per block); instances above kDedupMax are not checked.
+template <int CAP>
 __device__ __forceinline__ void dedup_body(const DedupArgs &a, int inst)
 {
-    __shared__ cx<double> proj[kDedupMax];
+    __shared__ cx<double> proj[CAP];
     if (inst >= a.n_inst) return;
     const long long g0 = (long long)inst * a.n_start;
     const TrackState S = a.s;
-    const bool check = a.n_start <= kDedupMax;
+    const bool check = a.n_start <= CAP;
     for (int b = threadIdx.x; check && b < a.n_start; b += blockDim.x) {
         const long long g = g0 + b;
         cx<double> p = {NAN, NAN};
@@ -489,15 +498,32 @@ __device__ __forceinline__ void dedup_body(const DedupArgs &a, int inst)
     }
 }
 
-__global__ __launch_bounds__(256) void k_dedup(const DedupArgs a) { dedup_body(a, blockIdx.x); }
+template <int CAP>
+__global__ __launch_bounds__(256) void k_dedup(const DedupArgs a) { dedup_body<CAP>(a, blockIdx.x); }
 
-__global__ __launch_bounds__(256) void k_dedup_many(const DedupArgs *a) { dedup_body(a[blockIdx.y], blockIdx.x); }
+template <int CAP>
+__global__ __launch_bounds__(256) void k_dedup_many(const DedupArgs *a)
+{
+    dedup_body<CAP>(a[blockIdx.y], blockIdx.x);
+}
+
+// The block's LDS capacity and size for instances of up to max_start paths
+// (above kDedupMax: the largest block; those instances are left unchecked).
+template <typename L>
+static hipError_t dedup_dispatch(int max_start, L launch)
+{
+    if (max_start <= 64) return launch(k_dedup_tag<64>{}, 64);
+    if (max_start <= 1024) return launch(k_dedup_tag<1024>{}, 256);
+    return launch(k_dedup_tag<kDedupMax>{}, 256);
+}
 
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st)
 {
     if (a.total == 0 || a.n_inst == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dedup, dim3((unsigned)a.n_inst), dim3(256), 0, st, a);
-    return hipGetLastError();
+    return dedup_dispatch(a.n_start, [&](auto tag, int threads) {
+        hipLaunchKernelGGL(k_dedup<decltype(tag)::cap>, dim3((unsigned)a.n_inst), dim3(threads), 0, st, a);
+        return hipGetLastError();
+    });
 }
 
 // ---------------------------------------------------------------- prep (a0/a2)
@@ -770,11 +796,14 @@ hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, h
     return hipGetLastError();
 }
 
-hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, hipStream_t st)
+hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, int max_start, hipStream_t st)
 {
     if (count == 0 || max_inst == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dedup_many, dim3((unsigned)max_inst, (unsigned)count), dim3(256), 0, st, a);
-    return hipGetLastError();
+    return dedup_dispatch(max_start, [&](auto tag, int threads) {
+        hipLaunchKernelGGL(k_dedup_many<decltype(tag)::cap>, dim3((unsigned)max_inst, (unsigned)count), dim3(threads),
+                           0, st, a);
+        return hipGetLastError();
+    });
 }
 
 template <int N>
