@@ -21,12 +21,13 @@ such as products of image coordinates) loop in parameter space instead; each
 segment follows the family's waypoints so that every leg is a linear
 coefficient homotopy that stays inside the family (`monodromy_family`).
 
-Usage (writes tests/golden/start_triang4.npz, start_triang3.npz or
-start_trifocal.npz and prints its sha256):
+Usage (writes tests/golden/start_triang4.npz, start_triang3.npz,
+start_trifocal.npz or start_fivept.npz and prints its sha256):
 
     python -m oracle.monodromy triang4
     python -m oracle.monodromy triang3
     python -m oracle.monodromy trifocal
+    python -m oracle.monodromy fivept
 """
 from __future__ import annotations
 
@@ -193,6 +194,15 @@ def main(argv):
         # TRIFOCAL_LOOPS loops, so the stored set is not certified complete
         p0, sols = monodromy_family(TF.Family, seed=4, stall=5, max_loops=TRIFOCAL_LOOPS)
         _save_trifocal(TF, S, p0, distinct_rows(sols, tol=TRIFOCAL_MERGE_TOL))
+        return
+    if name == "fivept":
+        import hc_inputs.fivept as FP
+        S = FP.fivept_system()
+        p0, sols = monodromy_family(FP.Family, seed=4, stall=10, max_loops=200)
+        eta, d = check(S, FP.coefficients(p0), sols)
+        print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
+        np.savez(FP.START_FILE, params0=p0, coef0=FP.coefficients(p0), solutions=sols)
+        print(FP.START_FILE, hashlib.sha256(open(FP.START_FILE, "rb").read()).hexdigest())
         return
     if name == "trifocal-consolidate":
         # the last step of the `trifocal` run alone, on a set stored before it
