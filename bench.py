@@ -214,6 +214,50 @@ def p3p_leg(ctx, hc, torch, steps, warmup):
     return out
 
 
+def fivept_leg(ctx, hc, torch, steps, warmup):
+    """5-point relative pose + depth batch (1024 noisy instances x 40 paths from
+    the monodromy start set, general-degree term lists, n = 16) in both
+    precisions, on device buffers."""
+    import hc_inputs.fivept as F
+    dev = torch.device("cuda:0")
+    S = F.fivept_system()
+    p0, sols = F.start_instance()
+    _, coef, _ = F.fivept_workload("fivept_batch1024")
+    n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
+    p = torch.from_numpy(coef).to(dev)
+    ps = torch.from_numpy(F.coefficients(p0)).to(dev)
+    start = torch.from_numpy(sols).to(dev)
+    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    wst = w_eval_terms(S, True) + w_lu(n)
+    out = {"workload": f"fivept_batch1024: {n_inst} noisy 5-point relative pose + depth instances (n=16, "
+                       f"{S.n_terms} terms of degree <= 3), parameter homotopy from a {n_start}-solution "
+                       f"monodromy start set ({n_inst * n_start:,} paths)"}
+    for mode in ("fp64", "mixed"):
+        opts = hc.default_opts(precision=mode)
+        for _ in range(warmup):
+            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
+        torch.cuda.synchronize()
+        profs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
+            profs.append(ctx.last_profile().as_dict())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        stn = st.cpu().numpy()
+        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
+                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
+                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
+                                          f"k_track_terms<1,{'float' if mode == 'mixed' else 'double'},true>")}
+        log(f"bench: 5-point pose {mode}: {dt * 1e3:.1f} ms/step, {n_inst / dt:.3e} solves/s")
+    ctx.free_system(sysh)
+    return out
+
+
 def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
     """Trifocal pose batch (instances of trifocal_batch1024, each solved from the
     monodromy start set along the family's two-leg parameter path) on device
@@ -401,7 +445,7 @@ def main():
                     help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
                     help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,p3p,"
-                         "trifocal,lu,serving")
+                         "fivept,trifocal,lu,serving")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -537,6 +581,11 @@ def main():
         log("bench: P3P batch")
         ctx.set_profiling(True)
         extras["p3p"] = p3p_leg(ctx, hc, torch, args.steps, 1)
+        ctx.set_profiling(False)
+    if not args.no_extras and "fivept" not in skip:
+        log("bench: 5-point relative pose + depth batch")
+        ctx.set_profiling(True)
+        extras["fivept"] = fivept_leg(ctx, hc, torch, max(2, args.steps // 2), 1)
         ctx.set_profiling(False)
     if not args.no_extras and "triangulation3" not in skip:
         log("bench: 3-view triangulation batch")
