@@ -437,13 +437,13 @@ static const int *eqdeg_of(const hc_system *s) { return s->layout == HC_LAYOUT_T
 static const int *sdeg_of(const hc_system *s) { return s->layout == HC_LAYOUT_TERMS ? s->d_sdeg : nullptr; }
 
 // Paths per work item.  Group layouts pop items from a device counter, so small
-// items balance the wavefronts (measured best: 2 paths per lane group); the
+// items balance the wavefronts (measured best: 1 path per lane group); the
 // one-path-per-lane layout has fixed items of 64 paths.
 static int choose_tracks_per_item(const hc_opts &o, int n_start, int lanes)
 {
     if (o.tracks_per_item > 0) return o.tracks_per_item;
     const int slots = 64 / lanes;
-    return std::max(1, std::min(n_start, lanes == 1 ? 64 : 2 * slots));
+    return std::max(1, std::min(n_start, lanes == 1 ? 64 : slots));
 }
 
 template <typename T>
@@ -830,7 +830,7 @@ hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_
     std::vector<std::pair<int, int>> cand;
     if (s->n >= 2) {
         const int g = lanes_for(s);
-        for (int per_group : {2, 4, 8, 16}) cand.push_back({g, per_group * (64 / g)});
+        for (int per_group : {1, 2, 4, 8}) cand.push_back({g, per_group * (64 / g)});
     }
     if (s->kind == HC_TOTAL_DEGREE && s->layout == HC_LAYOUT_DENSE)
         for (int tpi : {64, 128, 256}) cand.push_back({1, tpi});
