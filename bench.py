@@ -31,8 +31,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
 # 512 MiB device copy (profiles/k_track_grp_dense8_batch512.md, k_track_terms_triang4_batch4096.md)
 # for the workloads those runs cover; they belong to the kernel version profiled there and are not
 # measured live.  The trifocal counters cover 32 instances, not the bench's batch: no entry.
-PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 130.1e6, "k_track_grp<8,8,double,false>": 347.0e6,
-                          "k_track_terms<0,float,true>": 1836.0e6, "k_track_terms<0,double,true>": 1737.1e6}
+PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 170.2e6, "k_track_grp<8,8,double,false>": 406.1e6,
+                          "k_track_terms<0,float,true>": 2297.1e6, "k_track_terms<0,double,true>": 2138.2e6}
 SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
 
