@@ -26,14 +26,12 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
-# HBM bytes per tracking launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, calibrated on a
-# 512 MiB device copy (profiles/k_track_grp_dense8_batch512.md, k_track_terms_triang4_batch4096.md)
-# for the workloads those runs cover; they belong to the kernel version profiled there and are not
-# measured live.  The trifocal counters cover 32 instances, not the bench's batch: no entry.
-PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 170.2e6, "k_track_grp<8,8,double,false>": 406.1e6,
-                          "k_track_terms<0,float,true>": 2297.1e6, "k_track_terms<0,double,true>": 2138.2e6}
-SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks (FP32: packed)
+SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz, one value per lane
+# HBM bytes per tracking launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch, scaled by the
+# reading of a 512 MiB device copy in the same run), for the kernel versions profiled in profiles/; they are
+# not measured live, and a kernel changed since its counters were taken has no entry.
+PROFILED_TRAFFIC_BYTES = {}
 
 
 def w_lu(n: int) -> int:
@@ -43,7 +41,33 @@ def w_lu(n: int) -> int:
     return f + sum(8 * (n - k - 1) + 6 for k in range(n))
 
 
-def w_eval(n: int) -> int:
+# ---- the useful-FLOP count of the contract: per stage (one evaluation of [H_x | rhs] plus one solve)
+
+def w_stage_dense(n: int, T: int) -> int:
+    """Dense quadratic tables: 8nT (F) + 3n(n+1) (monomials) + 8n^2(n+1) (F_x,
+    affine per entry) + the solve."""
+    return 8 * n * T + 3 * n * (n + 1) + 8 * n * n * (n + 1) + w_lu(n)
+
+
+def w_stage_param(system) -> int:
+    """Linear parameter homotopy on term lists: 20 per term of H (the blend and
+    two contractions) + 12 per term of the Jacobian (the blend and one
+    multiply-add) + the solve."""
+    e = np.asarray(system.term_exp)
+    return 20 * e.shape[0] + 12 * int((e > 0).sum()) + w_lu(int(system.n))
+
+
+def useful_flops(info, n: int, w_stage: int) -> float:
+    """FLOPs the FP64 oracle's paths do in tracking (its own counters): per step
+    attempt 4 RK4 stages and the RK combine (16n), per corrector iteration one
+    stage; the endpoint refinement runs in another kernel and is not counted."""
+    att = info["steps"].astype(np.float64) + info["rejects"]
+    return float(np.sum((4.0 * att + info["newton_its"]) * w_stage + 16.0 * n * att))
+
+
+# ---- the kernels' own count (what the tracker executes per stage), reported beside
+
+def w_eval_kernel(n: int) -> int:
     """FLOPs to build [H_x | rhs] for a dense quadratic total-degree homotopy as the
     kernel does: per equation n^2 complex multiply-adds for the Jacobian row, 2n
     for L.x and x.J (F by Euler's identity), 2n to scale the row by t and 37 for
@@ -51,16 +75,16 @@ def w_eval(n: int) -> int:
     return n * (8 * n * n + 18 * n + 37)
 
 
-def w_stage(n: int) -> int:
-    return w_eval(n) + w_lu(n)
+def w_stage_kernel(n: int) -> int:
+    return w_eval_kernel(n) + w_lu(n)
 
 
 def w_term(d: int, blend: int) -> int:
-    """Algorithmic FLOPs of one term of degree d: the coefficient blend, the
-    monomial and the products of all but one factor by prefix and suffix
-    products (3d - 5 complex multiplies for d >= 2), F += c m (8) and one
-    multiply-add per factor into the Jacobian row (8 d); a linear term needs no
-    products (its Jacobian entry is c, an add), a constant only the add into F."""
+    """Kernel FLOPs of one term of degree d: the coefficient blend, the monomial
+    and the products of all but one factor by prefix and suffix products
+    (3d - 5 complex multiplies for d >= 2), F += c m (8) and one multiply-add per
+    factor into the Jacobian row (8 d); a linear term needs no products (its
+    Jacobian entry is c, an add), a constant only the add into F."""
     if d == 0:
         return blend + 2
     if d == 1:
@@ -68,9 +92,9 @@ def w_term(d: int, blend: int) -> int:
     return blend + 6 * (3 * d - 5) + 8 + 8 * d
 
 
-def w_eval_terms(system, param: bool) -> int:
-    """Algorithmic FLOPs of one evaluation of [H_x | rhs] from term lists: per
-    term w_term (parameter homotopy: 8 for the blend and c1 - c0), plus 37 per
+def w_eval_terms_kernel(system, param: bool) -> int:
+    """Kernel FLOPs of one evaluation of [H_x | rhs] from term lists: per term
+    w_term (parameter homotopy: 8 for the blend and c1 - c0), plus 37 per
     equation for G, gamma and the blend under total degree."""
     deg = np.asarray(system.term_exp).sum(axis=1)
     blend = 8 if param else 0
@@ -98,64 +122,123 @@ def time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch):
     return (t1 - t0) / steps, profs
 
 
-def roofline(profs, n, kind, flops_per_stage=None, kernel=None):
-    """Tracker launches of one mode.  The mixed-precision tracker is one launch of
-    k_track_grp<.., float, ..> whose escalated paths run their FP64 stages inside
-    the same launch, so both stage counts go to that launch."""
+def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, useful_source=None):
+    """Roofline of the dominant kernel of one mode: the tracking launch (in mixed
+    precision one launch of the FP32 tracker whose escalated paths run their
+    FP64 stages inside it).  achieved = useful FLOPs per launch / the launch's
+    mean duration from HIP events on its stream.  Useful FLOPs are the FP64
+    oracle's tracking work on this workload (useful_per_step, the same figure for
+    both precisions; `useful_source` says how it was counted), else the stages
+    the GPU ran x the contract's per-stage count.  The kernel's own count of what
+    it executes per stage is reported beside (achieved_kernel_count)."""
     key = "fp32" if kind == "fp32" else "fp64"
     ms = float(np.mean([p[f"ms_track_{key}"] for p in profs]))
-    launches = float(np.mean([p[f"launches_{key}"] for p in profs]))
+    launches = max(float(np.mean([p[f"launches_{key}"] for p in profs])), 1.0)
     stages = float(np.mean([p[f"stages_{key}"] + (p["stages_fp64"] if key == "fp32" else 0.0) for p in profs]))
-    wst = flops_per_stage if flops_per_stage is not None else w_stage(n)
-    flops = stages * wst
-    per_launch_ms = ms / max(launches, 1.0)
-    achieved = flops / launches / (per_launch_ms * 1e-3) / 1e12
+    per_launch_s = ms / launches * 1e-3
+    if useful_per_step is not None:
+        flops, src = float(useful_per_step), useful_source or "oracle"
+    else:
+        flops, src = stages * w_contract, "GPU-executed stages x the contract's per-stage count"
+    achieved = flops / launches / per_launch_s / 1e12
     peak = PEAK_TFLOPS[key]
-    kname = kernel or f"k_track_grp<8,8,{'float' if key == 'fp32' else 'double'},false>"
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": PROFILED_TRAFFIC_BYTES.get(kname),
-            "kernel": kname,
-            "kernel_ms_per_launch": round(per_launch_ms, 4), "launches_per_step": launches,
-            "stages_per_launch": stages / launches, "flops_per_stage": wst}
+    traffic = PROFILED_TRAFFIC_BYTES.get(kernel)
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic,
+           "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel version, profiles/ (not live)"
+           if traffic is not None else None,
+           "kernel": kernel, "kernel_ms_per_launch": round(ms / launches, 4), "launches_per_step": launches,
+           "flops_source": src, "flops_per_stage": w_contract, "useful_flops_per_launch": flops / launches,
+           "gpu_stages_per_launch": stages / launches, "flops_per_stage_kernel": w_kernel,
+           "achieved_kernel_count": round(stages * w_kernel / launches / per_launch_s / 1e12, 3)}
+    if key == "fp32":
+        out["frac_scalar_fp32"] = round(achieved / SCALAR_FP32_TFLOPS, 4)
+    return out
 
 
-def cpu_baseline(S, coef, gam, budget_s=12.0):
+def set_parity(ep_g, st_g, ep_o, st_o, ok_gpu=0):
+    """Endpoint error of the GPU's finite solutions against the FP64 oracle's,
+    instance by instance: a one-to-one pairing (nearest oracle root by k-d tree,
+    greedy when two GPU roots pick the same one), relative max-norm distance over
+    max(1, |x|).  Returns the worst distance, the instances whose finite counts
+    differ, and the failure rates of both sides."""
+    from scipy.spatial import cKDTree
+    worst, mismatch = 0.0, 0
+    for i in range(len(ep_o)):
+        fg = ep_g[i][st_g[i] == ok_gpu]
+        fo = ep_o[i][st_o[i] == 0]
+        if len(fg) != len(fo):
+            mismatch += 1
+            continue
+        if len(fo) == 0:
+            continue
+        emb = lambda z: np.concatenate([z.real, z.imag], axis=1)  # noqa: E731
+        _, j = cKDTree(emb(fg)).query(emb(fo), k=1, p=np.inf)
+        if len(np.unique(j)) != len(j):
+            free = np.ones(len(fg), bool)
+            j = np.zeros(len(fo), int)
+            for k, y in enumerate(fo):
+                d = np.where(free, np.max(np.abs(fg - y), axis=1), np.inf)
+                j[k] = int(np.argmin(d))
+                free[j[k]] = False
+        d = np.max(np.abs(fg[j] - fo), axis=1) / np.maximum(1.0, np.max(np.abs(fo), axis=1))
+        worst = max(worst, float(d.max()))
+    return {"instances": len(ep_o), "max_rel_err": worst, "finite_count_mismatches": mismatch,
+            "gpu_failure_rate": float(np.mean(st_g[:len(ep_o)] != ok_gpu)),
+            "oracle_failure_rate": float(np.mean(st_o != 0))}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(S, coef, gam, single_inst=8):
+    """The FP64 oracle (built -O3 -march=native) on the whole workload with every
+    host core, and on its first `single_inst` instances with one thread.  Also
+    returns the oracle's endpoints, statuses and counters for the parity and
+    useful-FLOP figures."""
     import oracle
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    lib = oracle.use_native_build()
+    threads = oracle.default_threads()    # every core of this process's CPU share
     t0 = time.perf_counter()
-    oracle.track(S, coef[:2], gam[:2], n_threads=threads)
-    rate_inst = 2 / (time.perf_counter() - t0)
-    k = int(min(len(coef), max(2, round(rate_inst * budget_s))))
-    t0 = time.perf_counter()
-    _, ost, _ = oracle.track(S, coef[:k], gam[:k], n_threads=threads)
+    oep, ost, oinfo = oracle.track(S, coef, gam, n_threads=threads)
     dt = time.perf_counter() - t0
-    paths = k * 256
-    return {"value": round(paths / dt, 1), "unit": "tracks/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {k} of the 512 instances ({paths} paths, FP64), {dt:.1f} s, "
-                      f"{threads} threads; success {np.mean(ost == 0):.4f}"}
+    n_start = oep.shape[1]
+    paths = len(coef) * n_start
+    t0 = time.perf_counter()
+    oracle.track(S, coef[:single_inst], gam[:single_inst], n_threads=1)
+    dt1 = time.perf_counter() - t0
+    res = {"value": round(paths / dt, 1), "unit": "tracks/s", "cores": threads, "kind": "oracle",
+           "sample": f"all {len(coef)} instances ({paths} paths, FP64) on {threads} threads in {dt:.1f} s; "
+                     f"one thread: first {single_inst} instances in {dt1:.1f} s",
+           "solves_per_s": round(len(coef) / dt, 2),
+           "single_thread_tracks_per_s": round(single_inst * n_start / dt1, 1),
+           "cpu_model": cpu_model(), "build": oracle.NATIVE_FLAGS, "library": os.path.basename(lib),
+           "success_frac": round(float(np.mean(ost == 0)), 5)}
+    return res, (oep, ost, oinfo)
 
 
-def vision_leg(ctx, hc, torch, steps, warmup, n_views=4):
-    """N-view triangulation batch (4096 instances; 4 views: 296 paths each, 3
-    views: 94; parameter homotopy from the monodromy start set) in both
-    precisions."""
-    import hc_inputs.vision as V
-    dev = torch.device("cuda:0")
-    S = V.triangulation_system(n_views)
-    c0, sols = V.start_instance(n_views)
-    _, coef, _ = V.vision_workload(f"triang{n_views}_batch4096")
-    n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
-    p = torch.from_numpy(coef).to(dev)
-    ps = torch.from_numpy(c0).to(dev)
-    start = torch.from_numpy(sols).to(dev)
-    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
-    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
-    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
-    sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
-    wst = w_eval_terms(S, True) + w_lu(n)
-    out = {"workload": f"triang{n_views}_batch4096: {n_inst} noisy {n_views}-view triangulation instances "
-                       f"(n={n}, {S.n_terms} terms), parameter homotopy from a {n_start}-solution monodromy "
-                       f"start set ({n_inst * n_start:,} paths)"}
+def oracle_sample(S, coef, start, c0, k):
+    """The oracle on the first k instances of a parameter-homotopy workload (all
+    host cores): endpoints, statuses, counters and the wall time."""
+    import oracle
+    t0 = time.perf_counter()
+    oep, ost, oinfo = oracle.track(S, coef[:k], start=start, coef0=c0, kind=oracle.LINEAR)
+    return oep, ost, oinfo, time.perf_counter() - t0
+
+
+def run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S, kernel_fmt,
+                    w_contract, w_kernel, useful_per_step, useful_source, osamp, n_inst, n_start):
+    """FP64 and mixed runs of one parameter-homotopy batch: timing, statuses,
+    roofline, endpoint error on the oracle's sampled instances."""
+    out = {}
+    oep, ost = osamp
     for mode in ("fp64", "mixed"):
         opts = hc.default_opts(precision=mode)
         for _ in range(warmup):
@@ -170,36 +253,76 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4):
         dt = (time.perf_counter() - t0) / steps
         stn = st.cpu().numpy()
         inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+        k = len(oep)
         out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
                      "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
                      "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
                      "escalated": int(inf["escalated"].sum()),
                      "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
-                     "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
-                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
-                                          f"k_track_terms<0,{'float' if mode == 'mixed' else 'double'},true>")}
-        log(f"bench: {n_views}-view triangulation {mode}: {dt * 1e3:.1f} ms/step, "
-            f"{n_inst * n_start / dt:.3e} tracks/s")
+                     "endpoint_error_vs_oracle": set_parity(ep[:k].cpu().numpy(), stn[:k], oep, ost),
+                     "profile": {q: float(np.mean([r[q] for r in profs])) for q in profs[0]},
+                     "roofline": roofline(profs, "fp32" if mode == "mixed" else "fp64",
+                                          kernel_fmt.format("float" if mode == "mixed" else "double"),
+                                          w_contract, w_kernel, useful_per_step, useful_source)}
+        log(f"bench: {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
     out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
     return out
 
 
-def p3p_leg(ctx, hc, torch, steps, warmup):
+def vision_leg(ctx, hc, torch, steps, warmup, n_views=4, sample=16):
+    """N-view triangulation batch (4096 instances; 4 views: 296 paths each, 3
+    views: 94; parameter homotopy from the monodromy start set) in both
+    precisions; the oracle runs the first `sample` instances."""
+    import hc_inputs.vision as V
+    dev = torch.device("cuda:0")
+    S = V.triangulation_system(n_views)
+    c0, sols = V.start_instance(n_views)
+    _, coef, _ = V.vision_workload(f"triang{n_views}_batch4096")
+    n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
+    oep, ost, oinfo, odt = oracle_sample(S, coef, sols, c0, sample)
+    w_c = w_stage_param(S)
+    useful = useful_flops(oinfo, n, w_c) / sample * n_inst
+    p = torch.from_numpy(coef).to(dev)
+    ps = torch.from_numpy(c0).to(dev)
+    start = torch.from_numpy(sols).to(dev)
+    ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
+    info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
+    sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    out = {"workload": f"triang{n_views}_batch4096: {n_inst} noisy {n_views}-view triangulation instances "
+                       f"(n={n}, {S.n_terms} terms; each camera pair's pose perturbed as the paper's 4-view "
+                       f"experiment does, so the critical points are isolated), parameter homotopy from a "
+                       f"{n_start}-solution monodromy start set ({n_inst * n_start:,} paths)",
+           "oracle_sample": f"first {sample} instances, {odt:.1f} s"}
+    out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
+                               "k_track_terms<0,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
+                               f"oracle counters of the first {sample} instances, scaled to {n_inst}",
+                               (oep, ost), n_inst, n_start))
+    ctx.free_system(sysh)
+    return out
+
+
+def p3p_leg(ctx, hc, torch, steps, warmup, sample=1024):
     """P3P batch (65536 noisy instances x 8 total-degree paths, dense tables with
-    n = 3) in both precisions, on device buffers."""
+    n = 3) in both precisions, on device buffers; the oracle runs the first
+    `sample` instances."""
+    import oracle
     import hc_inputs.p3p as P
     dev = torch.device("cuda:0")
     S, coef, gam, _ = P.p3p_workload("p3p_batch65536")
     n_inst, n_start, n = coef.shape[0], 8, S.n
+    oep, ost, oinfo = oracle.track(S, coef[:sample], gam[:sample])
+    T = 1 + n + n * (n + 1) // 2
+    w_c = w_stage_dense(n, T)
+    useful = useful_flops(oinfo, n, w_c) / sample * n_inst
     p = torch.from_numpy(coef).to(dev)
     g = torch.from_numpy(gam).to(dev)
     ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
     st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
     info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
     sysh = ctx.load_system(S)
-    wst = w_eval_terms(S, False) + w_lu(n)
     out = {"workload": f"p3p_batch65536: {n_inst} noisy P3P instances (3 quadratics in the depths, 13 terms), "
-                       f"total-degree homotopy, {n_inst * n_start:,} paths"}
+                       f"total-degree homotopy, {n_inst * n_start:,} paths; oracle on the first {sample}"}
     for mode in ("fp64", "mixed"):
         opts = hc.default_opts(precision=mode)
         dt, profs = time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch)
@@ -207,64 +330,59 @@ def p3p_leg(ctx, hc, torch, steps, warmup):
         out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
                      "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
                      "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
-                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
-                                          f"k_track_grp<3,4,{'float' if mode == 'mixed' else 'double'},false>")}
+                     "endpoint_error_vs_oracle": set_parity(ep[:sample].cpu().numpy(), stn[:sample], oep, ost),
+                     "roofline": roofline(profs, "fp32" if mode == "mixed" else "fp64",
+                                          f"k_track_grp<3,4,{'float' if mode == 'mixed' else 'double'},false>",
+                                          w_c, w_eval_terms_kernel(S, False) + w_lu(n), useful,
+                                          f"oracle counters of the first {sample} instances, scaled")}
         log(f"bench: P3P {mode}: {dt * 1e3:.2f} ms/step, {n_inst / dt:.3e} solves/s")
     ctx.free_system(sysh)
     return out
 
 
-def fivept_leg(ctx, hc, torch, steps, warmup):
+def fivept_leg(ctx, hc, torch, steps, warmup, sample=32):
     """5-point relative pose + depth batch (1024 noisy instances x 40 paths from
     the monodromy start set, general-degree term lists, n = 16) in both
-    precisions, on device buffers."""
+    precisions, on device buffers; the oracle runs the first `sample`."""
     import hc_inputs.fivept as F
     dev = torch.device("cuda:0")
     S = F.fivept_system()
     p0, sols = F.start_instance()
+    c0 = F.coefficients(p0)
     _, coef, _ = F.fivept_workload("fivept_batch1024")
     n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
+    oep, ost, oinfo, odt = oracle_sample(S, coef, sols, c0, sample)
+    w_c = w_stage_param(S)
+    useful = useful_flops(oinfo, n, w_c) / sample * n_inst
     p = torch.from_numpy(coef).to(dev)
-    ps = torch.from_numpy(F.coefficients(p0)).to(dev)
+    ps = torch.from_numpy(c0).to(dev)
     start = torch.from_numpy(sols).to(dev)
     ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
     st = torch.empty((n_inst, n_start), dtype=torch.int32, device=dev)
     info = torch.empty((n_inst, n_start, 32), dtype=torch.uint8, device=dev)
     sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
-    wst = w_eval_terms(S, True) + w_lu(n)
     out = {"workload": f"fivept_batch1024: {n_inst} noisy 5-point relative pose + depth instances (n=16, "
                        f"{S.n_terms} terms of degree <= 3), parameter homotopy from a {n_start}-solution "
-                       f"monodromy start set ({n_inst * n_start:,} paths)"}
-    for mode in ("fp64", "mixed"):
-        opts = hc.default_opts(precision=mode)
-        for _ in range(warmup):
-            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
-        torch.cuda.synchronize()
-        profs = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
-            profs.append(ctx.last_profile().as_dict())
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        stn = st.cpu().numpy()
-        out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
-                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
-                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
-                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
-                                          f"k_track_terms<1,{'float' if mode == 'mixed' else 'double'},true>")}
-        log(f"bench: 5-point pose {mode}: {dt * 1e3:.1f} ms/step, {n_inst / dt:.3e} solves/s")
+                       f"monodromy start set ({n_inst * n_start:,} paths); oracle on the first {sample}"}
+    out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
+                               "k_track_terms<1,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
+                               f"oracle counters of the first {sample} instances, scaled", (oep, ost), n_inst,
+                               n_start))
     ctx.free_system(sysh)
     return out
 
 
-def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
+TRIFOCAL_ORACLE_SAMPLE = os.path.join(ROOT, "tests", "golden", "trifocal_oracle_sample.npz")
+
+
+def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_fp64=256):
     """Trifocal pose batch (instances of trifocal_batch1024, each solved from the
     monodromy start set along the family's two-leg parameter path) on device
-    buffers; one step = both legs.  FP64 on n_inst instances (the full batch by
-    default); mixed precision, which escalates ~45% of these paths to FP64 and
-    so is slower here, on the first n_inst_mixed for comparison.  The warmup
-    runs on 8 instances (the full batch takes about a minute)."""
+    buffers; one step = both legs.  Mixed precision on n_inst instances (the
+    full batch by default), FP64 on the first n_inst_fp64.  The endpoint error
+    and the useful FLOPs come from the oracle's two-leg endpoints of sampled
+    instances stored by tests/golden/make_trifocal_oracle_sample.py (the oracle
+    takes about a minute per instance).  The warmup runs on 8 instances."""
     import hc_inputs.trifocal as TF
     dev = torch.device("cuda:0")
     S = TF.trifocal_system()
@@ -285,12 +403,17 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
     info = torch.empty_like(info1)
     nan = torch.full_like(ep1, complex(float("nan"), 0.0))
     sysh = ctx.load_system(S, kind=hc.HC_PARAMETER)
-    wst = w_eval_terms(S, True) + w_lu(n)
+    w_c = w_stage_param(S)
+    gold = None
+    if os.path.exists(TRIFOCAL_ORACLE_SAMPLE):
+        z = np.load(TRIFOCAL_ORACLE_SAMPLE)
+        if z["n_start"] == n_start and np.array_equal(z["sols_sha"], np.frombuffer(
+                __import__("hashlib").sha256(sols.tobytes()).digest(), np.uint8)):
+            gold = z
     out = {"workload": f"trifocal_batch1024: noisy trifocal-pose instances (n=18, 234 terms of degree <= 5), "
-                       f"two-leg parameter path from a {n_start}-solution monodromy start set; FP64 on "
-                       f"{n_inst} instances ({n_inst * n_start:,} paths per leg), mixed on the first "
-                       f"{n_inst_mixed}"}
-    for mode, ni in (("fp64", n_inst), ("mixed", n_inst_mixed)):
+                       f"two-leg parameter path from a {n_start}-solution monodromy start set; mixed on "
+                       f"{n_inst} instances ({n_inst * n_start:,} paths per leg), FP64 on the first {n_inst_fp64}"}
+    for mode, ni in (("mixed", n_inst), ("fp64", n_inst_fp64)):
         opts = hc.default_opts(precision=mode)
 
         def solve(profs, k):
@@ -318,15 +441,30 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_mixed=128):
             legs[name] = {"steps": float(inf["steps"].mean()), "rejects": float(inf["rejects"].mean()),
                           "newton_its": float(inf["newton_its"].mean()),
                           "escalated_frac": float(inf["escalated"].mean())}
-        out[mode] = {"instances": ni, "ms_per_step": dt * 1e3, "tracks_per_s": ni * n_start / dt,
-                     "solves_per_s": ni / dt,
-                     "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
-                     "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
-                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(), "legs": legs,
-                     "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64", wst,
-                                          f"k_track_terms<2,{'float' if mode == 'mixed' else 'double'},true>")}
+        useful = src = None
+        res = {"instances": ni, "ms_per_step": dt * 1e3, "tracks_per_s": ni * n_start / dt,
+               "solves_per_s": ni / dt, "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
+               "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
+               "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(), "legs": legs}
+        if gold is not None:
+            idx = [int(i) for i in gold["instances"] if i < ni]
+            if idx:
+                epn = ep[:ni].cpu().numpy()
+                res["endpoint_error_vs_oracle"] = set_parity(epn[idx], stn[idx], gold["endpoints"][:len(idx)],
+                                                             gold["status"][:len(idx)])
+                res["endpoint_error_vs_oracle"]["instances_checked"] = idx
+            # per leg, the oracle's tracking FLOPs of its sampled instances, scaled
+            # to this run's instances; a "launch" here is one leg
+            # one call = one leg: half the two legs' work per call on average
+            useful = float(gold["useful_flops_per_instance"]) * ni / 2
+            src = f"oracle counters of instances {list(gold['instances'])} (both legs), scaled to {ni}"
+        res["roofline"] = roofline(profs, "fp32" if mode == "mixed" else "fp64",
+                                   f"k_track_terms<2,{'float' if mode == 'mixed' else 'double'},true>", w_c,
+                                   w_eval_terms_kernel(S, True) + w_lu(n), useful, src)
+        out[mode] = res
         log(f"bench: trifocal {mode} ({ni} instances): {dt * 1e3:.1f} ms/step, {ni * n_start / dt:.3e} tracks/s "
             f"per leg")
+    ctx.free_system(sysh)
     return out
 
 
@@ -376,31 +514,46 @@ def lu_leg(ctx, hc, torch, sizes=(4, 8, 12, 16, 20), batches=(1000, 1 << 18), re
     return out
 
 
-def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="mixed"):
-    """Open-loop Poisson arrivals at `rate` requests/s into the serving loop.
-    Mix: 40% one dense n = 8 system with 256 paths (the throughput workload's
-    request), 40% one 4-view triangulation instance (296 paths from the resident
-    start set), 20% one dense system with n uniform in 5..10 and 2^n paths."""
-    import hc_inputs
-    import hc_inputs.vision as V
+def _serving_trace(rate, total, seed):
+    """Open-loop Poisson arrival times over `total` seconds and each request's
+    draw (kind, n, instance index), the same for every serving run."""
     rng = np.random.default_rng(seed)
-    systems = {n: ctx.load_system(hc_inputs.dense_quadratic_system(n)) for n in range(5, 11)}
-    pool = {n: hc_inputs.dense_quadratic_instances(n, 64, seed=900 + n) for n in range(5, 11)}
-    tri = ctx.load_system(V.triangulation_system(), kind=hc.HC_PARAMETER)
-    tri_c0, tri_sols = V.start_instance()
-    _, tri_coef, _ = V.triangulation_instances(64, seed=950)
-    srv = hc.Server(ctx, max_inflight=4, max_batch_requests=256, opts=hc.default_opts(precision=precision))
-    total = warm_s + meas_s
     gaps = rng.exponential(1.0 / rate, size=int(rate * total * 1.2) + 16)
     arrivals = np.cumsum(gaps)
     arrivals = arrivals[arrivals < total]
     kinds = rng.random(len(arrivals))
     ns = rng.integers(5, 11, size=len(arrivals))
     picks = rng.integers(0, 64, size=len(arrivals))
+    return arrivals, kinds, ns, picks
+
+
+def _serving_inputs(ctx, hc):
+    import hc_inputs
+    import hc_inputs.vision as V
+    systems = {n: ctx.load_system(hc_inputs.dense_quadratic_system(n)) for n in range(5, 11)}
+    pool = {n: hc_inputs.dense_quadratic_instances(n, 64, seed=900 + n) for n in range(5, 11)}
+    tri = ctx.load_system(V.triangulation_system(), kind=hc.HC_PARAMETER)
+    tri_c0, tri_sols = V.start_instance()
+    _, tri_coef, _ = V.triangulation_instances(64, seed=950)
+    return systems, pool, tri, tri_c0, tri_sols, tri_coef
+
+
+SERVE_MIX = "40% dense n=8 (256 paths), 40% 4-view triangulation (296 paths), 20% dense n in 5..10 (2^n paths)"
+
+
+def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="mixed"):
+    """Open-loop Poisson arrivals at `rate` requests/s into the serving loop
+    (continuous batching).  Mix: 40% one dense n = 8 system with 256 paths (the
+    throughput workload's request), 40% one 4-view triangulation instance (296
+    paths from the start set kept resident on the device), 20% one dense system
+    with n uniform in 5..10 and 2^n paths."""
+    systems, pool, tri, tri_c0, tri_sols, tri_coef = _serving_inputs(ctx, hc)
+    srv = hc.Server(ctx, max_inflight=4, max_batch_requests=256, opts=hc.default_opts(precision=precision))
+    tri_set = srv.add_start_set(tri, tri_sols, p_start=tri_c0)
+    arrivals, kinds, ns, picks = _serving_trace(rate, warm_s + meas_s, seed)
     tickets = []
     reset_done = False
     t0 = time.perf_counter()
-    paths = 0
     for k, ta in enumerate(arrivals):
         while time.perf_counter() - t0 < ta:
             pass
@@ -408,15 +561,11 @@ def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="m
             srv.reset_stats()
             reset_done = True
         if 0.4 <= kinds[k] < 0.8:
-            tickets.append(srv.submit(tri, tri_coef[picks[k]], start=tri_sols, p_start=tri_c0))
-            npaths = tri_sols.shape[0]
+            tickets.append(srv.submit(tri, tri_coef[picks[k]], start_set=tri_set))
         else:
             n = 8 if kinds[k] < 0.4 else int(ns[k])
             _, coef, gam = pool[n]
             tickets.append(srv.submit(systems[n], coef[picks[k]], gam[picks[k]]))
-            npaths = 2 ** n
-        if ta >= warm_s:
-            paths += npaths
     for t in tickets:
         srv.wait(t)
     st = srv.stats()
@@ -425,8 +574,41 @@ def serve_mix(ctx, hc, rate=2000.0, warm_s=1.0, meas_s=5.0, seed=5, precision="m
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
             "solves_per_s": round(st["completed"] / st["wall_s"], 1),
             "tracks_per_s": round(st["tracks_completed"] / st["wall_s"], 1), "batches": int(st["batches"]),
-            "mix": "40% dense n=8 (256 paths), 40% 4-view triangulation (296 paths), 20% dense n in 5..10 "
-                   f"(2^n paths); {precision} precision; 4 batches in flight, <= 256 requests per batch"}
+            "mix": f"{SERVE_MIX}; {precision} precision; 4 batches in flight, <= 256 requests per batch; the "
+                   f"triangulation start set resident on the device"}
+
+
+def serve_per_request(ctx, hc, rate=2000.0, warm_s=0.5, meas_s=1.5, seed=5):
+    """The comparator of the serving loop: the same arrival trace served by plain
+    per-request FP64 launches (one hc_track call per request, host buffers, in
+    arrival order, no batching).  Latency = completion - arrival; requests that
+    arrive while the device is busy wait in the queue."""
+    systems, pool, tri, tri_c0, tri_sols, tri_coef = _serving_inputs(ctx, hc)
+    arrivals, kinds, ns, picks = _serving_trace(rate, warm_s + meas_s, seed)
+    o64 = hc.default_opts(precision="fp64")
+    lat, paths = [], 0
+    t0 = time.perf_counter()
+    for k, ta in enumerate(arrivals):
+        while time.perf_counter() - t0 < ta:
+            pass
+        if 0.4 <= kinds[k] < 0.8:
+            ctx.track(tri, tri_coef[picks[k]], start=tri_sols, p_start=tri_c0, opts=o64)
+            npaths = tri_sols.shape[0]
+        else:
+            n = 8 if kinds[k] < 0.4 else int(ns[k])
+            _, coef, gam = pool[n]
+            ctx.track(systems[n], coef[picks[k]], gam[picks[k]], opts=o64)
+            npaths = 2 ** n
+        if ta >= warm_s:
+            lat.append(time.perf_counter() - t0 - ta)
+            paths += npaths
+    wall = time.perf_counter() - t0 - warm_s
+    lat = np.array(lat) * 1e3
+    return {"offered_rate": rate, "measured_s": meas_s, "requests": len(lat),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_ms": round(float(lat.max()), 3), "solves_per_s": round(len(lat) / wall, 1),
+            "tracks_per_s": round(paths / wall, 1),
+            "mix": f"{SERVE_MIX}; FP64; one hc_track call per request in arrival order"}
 
 
 def main():
@@ -442,10 +624,10 @@ def main():
                     help="first copy this many MiB device to device (a known-size kernel that calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters in a profiled run)")
     ap.add_argument("--trifocal-instances", type=int, default=1024,
-                    help="instances of the trifocal leg's FP64 batch (the full batch is 1024)")
+                    help="instances of the trifocal leg's mixed batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
                     help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,p3p,"
-                         "fivept,trifocal,lu,serving")
+                         "fivept,trifocal,lu,serving,serving_per_request")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -468,6 +650,7 @@ def main():
         del src, dst
     S, coef, gam = hc_inputs.workload("dense8_batch512")
     n_inst, n_start, n = coef.shape[0], 256, S.n
+    T = 1 + n + n * (n + 1) // 2
     p = torch.from_numpy(coef).to(dev)
     g = torch.from_numpy(gam).to(dev)
     ep = torch.empty((n_inst, n_start, n), dtype=torch.complex128, device=dev)
@@ -477,7 +660,7 @@ def main():
     ctx = hc.Context(0)
     sysh = ctx.load_system(S)
     ctx.set_profiling(True)
-    res = {}
+    res, profs_of, out_of = {}, {}, {}
     modes = ["fp64", "mixed"] if args.mode == "both" else [args.mode]
     for mode in modes:
         log(f"bench: {mode} batch, {args.warmup} warmup + {args.steps} timed steps")
@@ -485,6 +668,8 @@ def main():
         dt, profs = time_batch(ctx, sysh, p, g, ep, st, info, opts, args.steps, args.warmup, torch)
         stn = st.cpu().numpy()
         inf = info.cpu().numpy().view(hc.INFO_DTYPE).reshape(n_inst, n_start)
+        out_of[mode] = (ep.cpu().numpy(), stn)
+        profs_of[mode] = profs
         res[mode] = {
             "ms_per_step": dt * 1e3,
             "tracks_per_s": n_inst * n_start / dt,
@@ -493,9 +678,23 @@ def main():
             "escalated": int(inf["escalated"].sum()),
             "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
             "profile": {k: float(np.mean([q[k] for q in profs])) for k in profs[0]},
-            "roofline": roofline(profs, n, "fp32" if mode == "mixed" else "fp64"),
         }
         log(f"bench: {mode}: {dt * 1e3:.2f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
+
+    # the CPU oracle on the same workload: the baseline rate, and the reference
+    # for the endpoint error and the useful-FLOP count of the GPU runs
+    cpu, useful, useful_src = None, None, None
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline (all host cores, the whole workload; one thread on 8 instances)")
+        cpu, (oep, ost, oinfo) = cpu_baseline(S, coef, gam)
+        useful = useful_flops(oinfo, n, w_stage_dense(n, T))
+        useful_src = "FP64 oracle counters of the whole workload (4 stages per step attempt + corrector iterations)"
+        for mode in modes:
+            res[mode]["endpoint_error_vs_oracle"] = set_parity(out_of[mode][0], out_of[mode][1], oep, ost)
+    for mode in modes:
+        res[mode]["roofline"] = roofline(profs_of[mode], "fp32" if mode == "mixed" else "fp64",
+                                         f"k_track_grp<8,8,{'float' if mode == 'mixed' else 'double'},false>",
+                                         w_stage_dense(n, T), w_stage_kernel(n), useful, useful_src)
 
     extras = {}
     # the vector FMA rates the ALU roofline's peaks stand for, measured on this device
@@ -596,7 +795,7 @@ def main():
         log("bench: trifocal pose batch")
         ctx.set_profiling(True)
         extras["trifocal"] = trifocal_leg(ctx, hc, torch, 1, 1, n_inst=args.trifocal_instances,
-                                          n_inst_mixed=min(128, args.trifocal_instances))
+                                          n_inst_fp64=min(256, args.trifocal_instances))
         ctx.set_profiling(False)
     if not args.no_extras and "lu" not in skip:
         log("bench: standalone batched LU solves")
@@ -605,11 +804,9 @@ def main():
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
         extras["serving"] = serve_mix(ctx, hc)
         extras["serving_fp64"] = serve_mix(ctx, hc, precision="fp64")
-
-    cpu = None
-    if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        cpu = cpu_baseline(S, coef, gam)
+    if not args.no_extras and "serving_per_request" not in skip:
+        log("bench: serving comparator, plain per-request FP64 launches on the same arrival trace (0.5 s + 1.5 s)")
+        extras["serving_per_request_fp64"] = serve_per_request(ctx, hc)
 
     head = res["mixed"] if "mixed" in res else res["fp64"]
     out = {

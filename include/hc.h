@@ -89,8 +89,8 @@ typedef struct {
  *   c_k(p) = coef_const[k] + sum_{e = coef_rowptr[k]}^{coef_rowptr[k+1]-1} coef_val[e] * p[coef_col[e]].
  * coef_const may be NULL (all zero).  coef_rowptr == NULL selects the identity
  * map c = p (then n_params must equal n_terms and coef_col/coef_val are ignored).
- * The GPU path requires every term to have total degree <= 2 and every
- * equation degree >= 1. */
+ * The GPU path takes terms of total degree <= 8 (degree <= 2 for the dense
+ * table layout, see hc_layout) and needs every equation of degree >= 1. */
 typedef struct {
     int32_t n;
     int32_t n_terms;
@@ -127,7 +127,10 @@ typedef struct {
                            from a hand-over to FP64 (mixed mode) or a
                            crossing-check restart                             (5000)  */
     int32_t max_refine; /* endpoint Newton iterations                          (10)    */
-    int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end (0) */
+    int32_t steps_per_launch; /* steps per path per kernel launch, 0 = to the end;
+                                 -1 = the autotuner's choice if one applies, else
+                                 0 (hc_autotune with -1 also tries chunked
+                                 launches)                                        (0)     */
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
     int32_t lanes_per_path;   /* 1: one path per lane; 4 or 8: one row of [H_x | rhs]
                                  per lane, 4 or 8 lanes per path (dense tables);
@@ -143,13 +146,19 @@ typedef struct {
                                  refinement)                                      (0)     */
     int32_t crossing_check;   /* mixed mode: after refinement, paths of one instance
                                  that ended on the same root (relative distance
-                                 <= 1e-8; n_start <= 8192) start over in FP64    (1)     */
+                                 <= 1e-8) start over in FP64; instances above 8192
+                                 paths take 16 more workspace bytes per path  (1)     */
     int32_t per_instance_start; /* 1: every instance has its own start system:
                                  start is [n_inst][n_start][n] and, for
                                  HC_PARAMETER, p_start [n_inst][n_params] (the
                                  second leg of a piecewise-linear parameter path
                                  starts from the first leg's endpoints);
                                  hc_track and hc_track_device only           (0)     */
+    int32_t table_layout;     /* hc_layout of the evaluation tables: 0 (AUTO) = the
+                                 system's own; the other layout runs on a copy of
+                                 the system in that layout, made on first use (an
+                                 allocation); HC_E_UNSUPPORTED if that layout
+                                 cannot hold the system; 0 = autotuned        (0)     */
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;
@@ -287,29 +296,56 @@ typedef struct {
     hc_track_info *info;      /* [n_inst][n_start] or NULL                   */
 } hc_job;
 
-/* Tracks every path of n_jobs jobs that may differ in system, n (2..8), kind,
- * path count and instance count, with one persistent kernel per precision pass
- * and homotopy kind: its wavefronts pop work items (job, instance, range of
- * paths) from a device queue until it is empty, larger n first.  Options are
- * shared (opts->steps_per_launch must be 0; the layout is lanes_per_path 0).
- * Enqueued on `stream`; outputs valid after the stream is synchronised.  Each
- * job's results equal those of hc_track_device on that job alone.
+/* Tracks every path of n_jobs jobs that may differ in system, n (2..HC_MAX_N),
+ * table layout, kind, path count and instance count, with one persistent
+ * kernel per table kind, homotopy kind and precision pass: its wavefronts pop
+ * work items (job, instance, range of paths) from a device queue until it is
+ * empty, larger n first.  Options are shared (opts->steps_per_launch must be 0
+ * or -1, lanes_per_path 0, table_layout 0, per_instance_start 0).  With
+ * opts->use_graph and a non-null stream, the launch sequence is captured in a
+ * hipGraph on the first call and replayed by later calls with the same jobs
+ * array contents, options, stream and systems (profiling off): the inputs may
+ * change in place between calls, the job list may not.  Enqueued on `stream`;
+ * outputs valid after the stream is synchronised.  Each job's results equal
+ * those of hc_track_device on that job alone.
  * Errors: HC_E_INVALID, HC_E_UNSUPPORTED (n = 1, steps_per_launch > 0,
- * lanes_per_path = 1), HC_E_OOM, HC_E_DEVICE. */
+ * lanes_per_path = 1, per_instance_start), HC_E_OOM, HC_E_DEVICE. */
 hc_status hc_track_batch_device(hc_ctx *ctx, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts,
                                 void *stream);
 
-/* Autotuner: runs hc_track_device with each candidate work decomposition
- * (lanes per path, paths per wavefront work item) on these inputs, times it with
- * HIP events on `stream`, and writes the fastest into *best (other fields copied
- * from opts).  The choice is remembered in the context and used by later calls
- * with tracks_per_item = lanes_per_path = 0 on the same (system, precision,
- * n_start, n_inst).  The output buffers hold the last trial's results.
- * Errors: as hc_track_device. */
+/* Autotuner: runs hc_track_device with each candidate work decomposition on
+ * these inputs, times it with HIP events on `stream`, and writes the fastest
+ * into *best (other fields copied from opts).  Candidates: the evaluation-table
+ * layout (the system's own, and the other one where it can hold the system),
+ * lanes per path (one row of [H_x | rhs] per lane, or one path per lane for
+ * dense total-degree tables), paths per wavefront work item, and, when
+ * opts->steps_per_launch is -1, steps per launch (0, 64, 512).  The choice is
+ * remembered in the context under the workload's shape (device architecture,
+ * table layout, homotopy kind, n, term count, degrees, precision, n_start,
+ * n_inst) and used by later calls that leave table_layout, lanes_per_path and
+ * tracks_per_item at 0 (steps_per_launch only where the call passes -1), on
+ * any system of that shape.  When the environment variable HC_TUNE_CACHE named
+ * a file at hc_create, the context loaded it then and hc_autotune rewrites it
+ * with every choice made so far.  The output buffers hold the last trial's
+ * results.  Errors: as hc_track_device; HC_E_INVALID if the cache file cannot
+ * be written. */
 hc_status hc_autotune(hc_ctx *ctx, const hc_system *sys, const hc_c64 *start, int32_t n_start,
                       const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst, const hc_c64 *gamma,
                       const hc_opts *opts, hc_c64 *endpoints, int32_t *status, hc_track_info *info,
                       void *stream, hc_opts *best);
+
+/* Writes every autotuner choice of the context to the text file `path`, one
+ * per line ("<key> -> <layout> <lanes_per_path> <tracks_per_item>
+ * <steps_per_launch>").  Errors: HC_E_INVALID (NULL argument, file not
+ * writable). */
+hc_status hc_tune_save(hc_ctx *ctx, const char *path);
+
+/* Merges the choices stored in `path` (as written by hc_tune_save) into the
+ * context; entries of another device architecture never match this device's
+ * keys.  *n_loaded (may be NULL) receives the number of entries read.  Errors:
+ * HC_E_INVALID (NULL argument, file not readable, a malformed line: then
+ * nothing is merged). */
+hc_status hc_tune_load(hc_ctx *ctx, const char *path, int32_t *n_loaded);
 
 /* ---- serving: continuous batching of solve requests (host buffers) ---------- */
 
@@ -322,6 +358,10 @@ typedef struct {
     int64_t hbm_budget;         /* device bytes for the requests in flight   (8 GiB) */
     hc_opts opts;               /* tracking options of every request (mixed precision) */
 } hc_server_opts;
+
+/* A start set (start points and start parameters) kept on the server's device
+ * (hc_server_add_start_set). */
+typedef struct hc_start_set hc_start_set;
 
 /* One solve request: the hc_track arguments in host memory.  Inputs are copied
  * at submission; outputs are written when the request completes. */
@@ -336,6 +376,9 @@ typedef struct {
     hc_c64 *endpoints;          /* [n_inst][n_start][n]                     */
     int32_t *status;            /* [n_inst][n_start]                        */
     hc_track_info *info;        /* [n_inst][n_start] or NULL                */
+    const hc_start_set *start_set; /* or NULL; when set, the request tracks from
+                                   this resident set: start and p_start must be
+                                   NULL and n_start the set's count         */
 } hc_request;
 
 typedef struct {
@@ -358,6 +401,16 @@ void hc_server_default_opts(hc_server_opts *o);
  * the server.  Errors: HC_E_INVALID, HC_E_UNSUPPORTED (opts.steps_per_launch > 0
  * or lanes_per_path = 1), HC_E_OOM, HC_E_DEVICE. */
 hc_status hc_server_create(hc_ctx *ctx, const hc_server_opts *opts, hc_server **out);
+
+/* Uploads start points [n_start][n] (and, for HC_PARAMETER, the start
+ * parameters p_start [n_params]) of `sys` once; requests that name the returned
+ * set track from them without copying them (resident start sets: the serving
+ * loop's solve requests of one family share them).  The set lives on the
+ * device until hc_server_destroy.  Thread-safe.  Errors: HC_E_INVALID (NULL
+ * argument, n_start < 1, no p_start for a parameter homotopy, system on another
+ * device), HC_E_OOM, HC_E_DEVICE. */
+hc_status hc_server_add_start_set(hc_server *srv, const hc_system *sys, const hc_c64 *start, int32_t n_start,
+                                  const hc_c64 *p_start, const hc_start_set **out);
 
 /* Queues a request; *ticket identifies it.  Thread-safe.  The output buffers
  * must stay valid until the request completes.  Errors: HC_E_INVALID,

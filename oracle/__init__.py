@@ -44,14 +44,19 @@ DEFAULTS = dict(h0=0.05, h_min=1e-7, h_max=0.1, beta_inc=2.0, beta_dec=0.5, tau=
                 max_steps=5000, max_refine=10)
 
 
+# Host threads at most: the CPU share a process gets beside one GPU on the
+# machines this runs on (their nproc shows the whole host).
+MAX_THREADS = 16
+
+
 def default_threads() -> int:
     """Host threads the tracker uses by default: the cores this process may run
-    on, at most 16."""
+    on, at most MAX_THREADS."""
     try:
         n = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    return max(1, min(n, MAX_THREADS))
 
 
 def default_opts(**kw) -> Opts:
@@ -80,13 +85,42 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+# The CPU baseline's build of the same source: tuned for the host it runs on.
+# Auto-vectorisation stays off: gcc 11's AVX-512 code for the LU's row swap
+# assumes 32-byte alignment of rows that are 16 bytes apart and faults, and the
+# scalar complex arithmetic gains nothing from it (measured on the CPU).
+NATIVE_FLAGS = "-O3 -march=native -fno-tree-vectorize"
+_NATIVE_LIB = os.path.join(_HERE, "liborc_native.so")
+
+
+def build_native() -> str:
+    """Compile hc_oracle.c with NATIVE_FLAGS into liborc_native.so (on the host
+    that will run it: -march=native)."""
+    tmp = _NATIVE_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *NATIVE_FLAGS.split(), "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC,
+                           "-lm", "-lpthread"])
+    os.replace(tmp, _NATIVE_LIB)
+    return _NATIVE_LIB
+
+
+def use_native_build() -> str:
+    """Switch this process's oracle to the NATIVE_FLAGS build; returns its path."""
+    global _lib, _lib_path
+    path = build_native()
+    _lib = None
+    _lib_path = path
+    _load()
+    return path
+
+
 _lib = None
+_lib_path = None
 
 
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        lib = ctypes.CDLL(_lib_path or build())
         P = ctypes.c_void_p
         lib.orc_track_batch.restype = ctypes.c_int
         lib.orc_track_batch.argtypes = [ctypes.POINTER(_System), ctypes.c_int, P, P, P, P,

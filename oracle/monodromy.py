@@ -28,6 +28,12 @@ start_trifocal.npz or start_fivept.npz and prints its sha256):
     python -m oracle.monodromy triang3
     python -m oracle.monodromy trifocal
     python -m oracle.monodromy fivept
+
+The trifocal set can also be grown from a stored one (trifocal-resume
+[--seed=S] [--checkpoint=PATH]); trifocal-check writes an independent run from
+its own parameter point (tests/golden/trifocal_check.npz) and trifocal-compare
+carries each run's set to the other's parameter point and records what either
+misses.
 """
 from __future__ import annotations
 
@@ -94,6 +100,13 @@ def _close(sols, orbit):
     return distinct_rows(np.concatenate([sols, orbit(sols).reshape(-1, sols.shape[1])]))
 
 
+def _close_tol(sols, orbit, tol):
+    """`_close` with a merge tolerance."""
+    if orbit is None or len(sols) == 0:
+        return sols
+    return distinct_rows(np.concatenate([sols, orbit(sols).reshape(-1, sols.shape[1])]), tol)
+
+
 def monodromy(system, seed=0, stall=10, max_loops=500, n_threads=None, log=print, orbit=None, target=None):
     """(c0, solutions [N, n]) of a generic instance of the linear-coefficient
     family with the support of `system`.  `orbit`, if given, maps solutions to
@@ -133,17 +146,23 @@ def _path(family, system, p_from, p_to, sols, n_threads):
 
 
 def monodromy_family(family, seed=0, stall=10, max_loops=500, n_threads=None, log=print, target=None,
-                     on_loop=None):
+                     on_loop=None, tol=1e-8, resume=None):
     """(p0, solutions [N, n]) of a generic member of a structured parameter
     family (one whose coefficients are not free: `family` supplies the system,
     c(p), the waypoints of a path between two parameter points, random
     parameter points, a fabricated start pair and the solution symmetries).
     Loops p0 -> pa -> pb -> p0 as in `monodromy`; on_loop(p0, sols), if given,
-    sees the set after every loop."""
+    sees the set after every loop.  Endpoints closer than `tol` (relative) are
+    one solution.  resume = (p0, sols) continues the loops from a set found
+    before (the seed then only draws the loop parameters)."""
     system = family.system()
     rng = np.random.default_rng(seed)
-    p0, x0 = family.fabricate(rng)
-    sols = _close(x0[None, :], family.orbit)
+    if resume is None:
+        p0, x0 = family.fabricate(rng)
+        sols = _close(x0[None, :], family.orbit)
+    else:
+        p0, sols = resume
+        sols = distinct_rows(np.asarray(sols), tol)
     quiet = 0
     t0 = time.time()
     for loop in range(max_loops):
@@ -151,7 +170,8 @@ def monodromy_family(family, seed=0, stall=10, max_loops=500, n_threads=None, lo
         xa = _path(family, system, p0, pa, sols, n_threads)
         xb = _path(family, system, pa, pb, xa, n_threads)
         back = _path(family, system, pb, p0, xb, n_threads)
-        merged = _close(distinct_rows(np.concatenate([sols, back])), family.orbit) if len(back) else sols
+        merged = _close_tol(distinct_rows(np.concatenate([sols, back]), tol), family.orbit, tol) if len(back) \
+            else sols
         grew = len(merged) - len(sols)
         sols = merged
         quiet = 0 if grew > 0 else quiet + 1
@@ -170,30 +190,98 @@ def check(system, c0, sols):
     return eta, d
 
 
-TRIFOCAL_LOOPS = 19
+# A run ends after this many consecutive loops without a new solution.
+TRIFOCAL_STALL = 10
 # Roots of the trifocal family closer than this (relative) are one root: FP64
 # refinement of its worst-conditioned roots (condition numbers up to 1e13)
 # leaves copies ~1e-8 apart, while distinct roots are >= 1e-4 apart.
 TRIFOCAL_MERGE_TOL = 1e-6
+TRIFOCAL_CHECK_FILE = os.path.join(ROOT, "tests", "golden", "trifocal_check.npz")
 
 
-def _save_trifocal(TF, S, p0, sols):
+def _save_trifocal(TF, S, p0, sols, out, **extra):
     eta, d = check(S, TF.coefficients(p0), sols)
-    print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
-    out = TF.START_FILE
-    np.savez(out, params0=p0, coef0=TF.coefficients(p0), solutions=sols)
-    print(out, hashlib.sha256(open(out, "rb").read()).hexdigest())
+    print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}", flush=True)
+    np.savez(out, params0=p0, coef0=TF.coefficients(p0), solutions=sols, **extra)
+    print(out, hashlib.sha256(open(out, "rb").read()).hexdigest(), flush=True)
+
+
+def _trifocal_run(TF, seed, resume=None, checkpoint=None, n_threads=None):
+    """Monodromy on the trifocal family to the stall rule; every loop's set is
+    written to `checkpoint` (if given), so a stopped run can be resumed."""
+    def on_loop(p0, sols):
+        if checkpoint:
+            np.savez(checkpoint, params0=p0, solutions=sols)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    return monodromy_family(TF.Family, seed=seed, stall=TRIFOCAL_STALL, max_loops=100000, log=log,
+                            tol=TRIFOCAL_MERGE_TOL, resume=resume, on_loop=on_loop, n_threads=n_threads)
+
+
+def _carry(TF, S, p_from, p_to, sols, n_threads=None):
+    """Distinct finite endpoints of `sols` carried from p_from to p_to along the
+    family's two legs."""
+    out = _path(TF.Family, S, p_from, p_to, sols, n_threads)
+    return distinct_rows(out, TRIFOCAL_MERGE_TOL) if len(out) else out
+
+
+def _trifocal_main(cmd, opts):
+    import hc_inputs.trifocal as TF
+    S = TF.trifocal_system()
+    ckpt = opts.get("checkpoint")
+    nt = int(opts["threads"]) if "threads" in opts else None
+    if cmd == "trifocal":
+        # from one fabricated pair (seed 4) to the stall rule
+        p0, sols = _trifocal_run(TF, 4, checkpoint=ckpt, n_threads=nt)
+        _save_trifocal(TF, S, p0, sols, TF.START_FILE)
+    elif cmd == "trifocal-resume":
+        # more loops (drawn from --seed) on a set written before by this script:
+        # the stored set, or the checkpoint of a stopped run
+        src = ckpt if ckpt and os.path.exists(ckpt) else TF.START_FILE
+        z = np.load(src)
+        p0, sols = _trifocal_run(TF, int(opts.get("seed", 40)), resume=(z["params0"], z["solutions"]),
+                                 checkpoint=ckpt, n_threads=nt)
+        _save_trifocal(TF, S, p0, sols, TF.START_FILE)
+    elif cmd == "trifocal-check":
+        # an independent run: its own fabricated pair (seed 5), so its own
+        # generic parameter point, to the stall rule
+        if ckpt and os.path.exists(ckpt):
+            z = np.load(ckpt)
+            p0, sols = _trifocal_run(TF, int(opts.get("seed", 50)), resume=(z["params0"], z["solutions"]),
+                                     checkpoint=ckpt, n_threads=nt)
+        else:
+            p0, sols = _trifocal_run(TF, 5, checkpoint=ckpt, n_threads=nt)
+        _save_trifocal(TF, S, p0, sols, TRIFOCAL_CHECK_FILE)
+    elif cmd == "trifocal-compare":
+        # both sets carried to the other run's parameter point: a complete set
+        # reaches every root of the other (what the homotopy loses on the way
+        # is counted, not hidden)
+        a, b = np.load(TF.START_FILE), np.load(TRIFOCAL_CHECK_FILE)
+        ab = _carry(TF, S, b["params0"], a["params0"], b["solutions"], nt)
+        ba = _carry(TF, S, a["params0"], b["params0"], a["solutions"], nt)
+
+        def diff(x, ref):
+            ref = np.asarray(ref)
+            miss = 0
+            for y in ref:
+                d = np.max(np.abs(x - y), axis=1) / max(1.0, np.max(np.abs(y))) if len(x) else [np.inf]
+                miss += np.min(d) > TRIFOCAL_MERGE_TOL
+            return int(miss)
+        rep = dict(n_start=len(a["solutions"]), n_check=len(b["solutions"]), check_carried=len(ab),
+                   start_carried=len(ba), start_roots_not_reached=diff(ab, a["solutions"]),
+                   check_roots_not_reached=diff(ba, b["solutions"]),
+                   carried_not_in_start=diff(a["solutions"], ab), carried_not_in_check=diff(b["solutions"], ba))
+        print(rep, flush=True)
+        _save_trifocal(TF, S, b["params0"], b["solutions"], TRIFOCAL_CHECK_FILE,
+                       compare=np.array([rep[k] for k in sorted(rep)]), compare_keys=np.array(sorted(rep)))
+    else:
+        raise SystemExit(f"unknown command {cmd}")
 
 
 def main(argv):
     name = argv[1] if len(argv) > 1 else "triang4"
-    if name == "trifocal":
-        import hc_inputs.trifocal as TF
-        S = TF.trifocal_system()
-        # the run's tail finds a few new solutions every few loops; it is cut at
-        # TRIFOCAL_LOOPS loops, so the stored set is not certified complete
-        p0, sols = monodromy_family(TF.Family, seed=4, stall=5, max_loops=TRIFOCAL_LOOPS)
-        _save_trifocal(TF, S, p0, distinct_rows(sols, tol=TRIFOCAL_MERGE_TOL))
+    opts = dict(a[2:].split("=", 1) for a in argv[2:] if a.startswith("--") and "=" in a)
+    if name.startswith("trifocal"):
+        _trifocal_main(name, opts)
         return
     if name == "fivept":
         import hc_inputs.fivept as FP
@@ -203,13 +291,6 @@ def main(argv):
         print(f"{len(sols)} solutions, max residual {eta:.2e}, distinct {d}")
         np.savez(FP.START_FILE, params0=p0, coef0=FP.coefficients(p0), solutions=sols)
         print(FP.START_FILE, hashlib.sha256(open(FP.START_FILE, "rb").read()).hexdigest())
-        return
-    if name == "trifocal-consolidate":
-        # the last step of the `trifocal` run alone, on a set stored before it
-        # existed: the result is the file a full run writes
-        import hc_inputs.trifocal as TF
-        z = np.load(TF.START_FILE)
-        _save_trifocal(TF, TF.trifocal_system(), z["params0"], distinct_rows(z["solutions"], tol=TRIFOCAL_MERGE_TOL))
         return
     if name not in ("triang4", "triang3"):
         raise SystemExit(f"unknown family {name}")

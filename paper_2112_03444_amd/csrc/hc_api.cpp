@@ -9,8 +9,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -35,7 +38,7 @@ hc_status fail(hc_status code, const char *fmt, ...)
     return code;
 }
 
-void clear_error() { clear_error(); }
+void clear_error() { g_err.clear(); }
 
 const char *last_error() { return g_err.c_str(); }
 
@@ -99,10 +102,27 @@ hc_status hc_create(int device, hc_ctx **out)
     hc_ctx *c = new (std::nothrow) hc_ctx;
     if (!c) return fail(HC_E_OOM, "hc_create: out of host memory");
     c->device = device;
-    hipError_t e = hipStreamCreate(&c->own_stream);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        c->arch = c->arch.substr(0, c->arch.find(':'));  // gfx950, without feature flags
+        e = hipStreamCreate(&c->own_stream);
+    }
     if (e != hipSuccess) {
         delete c;
-        return fail(HC_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        return fail(HC_E_DEVICE, "hc_create: %s", hipGetErrorString(e));
+    }
+    // a persisted autotuner cache, if HC_TUNE_CACHE names one (a missing file is
+    // created by the first hc_autotune)
+    if (const char *f = std::getenv("HC_TUNE_CACHE")) {
+        c->tune_file = f;
+        int32_t loaded = 0;
+        std::ifstream probe(c->tune_file);
+        if (probe.good() && hc_tune_load(c, f, &loaded) != HC_OK) {
+            hc_destroy(c);
+            return fail(HC_E_INVALID, "hc_create: HC_TUNE_CACHE file %s is malformed", f);
+        }
     }
     *out = c;
     return HC_OK;
@@ -110,6 +130,11 @@ hc_status hc_create(int device, hc_ctx **out)
 
 static void free_system_tables(hc_system *s)
 {
+    if (s->alt) {
+        free_system_tables(s->alt);
+        delete s->alt;
+        s->alt = nullptr;
+    }
     (void)hipFree(s->d_slot_ptr);
     (void)hipFree(s->d_slot_term);
     (void)hipFree(s->d_slot_mult);
@@ -137,6 +162,7 @@ void hc_destroy(hc_ctx *c)
     c->counter.release();
     c->queue.release();
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->bgraph_exec) (void)hipGraphExecDestroy(c->bgraph_exec);
     for (hipEvent_t &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -148,9 +174,13 @@ hc_status hc_load_system(hc_ctx *c, const hc_system_desc *d, hc_system **out)
     return hc_load_system_layout(c, d, HC_LAYOUT_AUTO, out);
 }
 
-hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layout, hc_system **out)
+}  // extern "C"
+
+// Validates a description and uploads its tables in `layout`; the system is
+// added to the context's list when `owned` (else its caller owns it: the
+// autotuner's copy in the other layout).
+static hc_status load_system_impl(hc_ctx *c, const hc_system_desc *d, int32_t layout, bool owned, hc_system **out)
 {
-    clear_error();
     if (!c || !d || !out) return fail(HC_E_INVALID, "hc_load_system: NULL argument");
     if (d->n < 1) return fail(HC_E_INVALID, "hc_load_system: n = %d", d->n);
     if (d->n > HC_MAX_N) return fail(HC_E_UNSUPPORTED, "hc_load_system: n = %d > %d", d->n, HC_MAX_N);
@@ -328,9 +358,51 @@ hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layo
         delete s;
         return fail(e == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "hc_load_system: %s", hipGetErrorString(e));
     }
-    c->systems.push_back(s);
+    // host copy of the description
+    s->h_term_eq.assign(d->term_eq, d->term_eq + nt);
+    s->h_term_exp.assign(d->term_exp, d->term_exp + (size_t)nt * n);
+    if (d->coef_const) s->h_const.assign(d->coef_const, d->coef_const + nt);
+    if (d->coef_rowptr) {
+        s->h_rowptr.assign(d->coef_rowptr, d->coef_rowptr + nt + 1);
+        s->h_col.assign(d->coef_col, d->coef_col + nnz);
+        s->h_val.assign(d->coef_val, d->coef_val + nnz);
+    }
+    if (owned) c->systems.push_back(s);
     *out = s;
     return HC_OK;
+}
+
+// The system in the other table layout (dense tables <-> term lists), loaded
+// from its stored description on first use; null if that layout cannot hold it.
+static hc_system *alt_layout(hc_ctx *c, const hc_system *s)
+{
+    if (s->alt) return s->alt;
+    const int other = s->layout == HC_LAYOUT_DENSE ? HC_LAYOUT_TERMS : HC_LAYOUT_DENSE;
+    if (other == HC_LAYOUT_DENSE && (s->n > 8 || s->max_deg > 2)) return nullptr;
+    if (other == HC_LAYOUT_TERMS && s->n < 2) return nullptr;
+    hc_system_desc d{};
+    d.n = s->n;
+    d.n_terms = s->n_terms;
+    d.term_eq = s->h_term_eq.data();
+    d.term_exp = s->h_term_exp.data();
+    d.n_params = s->n_params;
+    d.kind = s->kind;
+    d.coef_const = s->h_const.empty() ? nullptr : s->h_const.data();
+    d.coef_rowptr = s->h_rowptr.empty() ? nullptr : s->h_rowptr.data();
+    d.coef_col = s->h_col.empty() ? nullptr : s->h_col.data();
+    d.coef_val = s->h_val.empty() ? nullptr : s->h_val.data();
+    hc_system *a = nullptr;
+    if (load_system_impl(c, &d, other, false, &a) != HC_OK) return nullptr;
+    const_cast<hc_system *>(s)->alt = a;
+    return a;
+}
+
+extern "C" {
+
+hc_status hc_load_system_layout(hc_ctx *c, const hc_system_desc *d, int32_t layout, hc_system **out)
+{
+    clear_error();
+    return load_system_impl(c, d, layout, true, out);
 }
 
 hc_status hc_free_system(hc_ctx *c, hc_system *s)
@@ -345,6 +417,7 @@ hc_status hc_free_system(hc_ctx *c, hc_system *s)
     delete s;
     c->systems.erase(it);
     c->graph_valid = false;
+    c->bgraph_valid = false;
     return HC_OK;
 }
 
@@ -393,8 +466,10 @@ static hc_status check_opts(const hc_opts &o)
         return fail(HC_E_INVALID, "opts.precision = %d", o.precision);
     if (!(o.h0 > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.beta_dec > 0 && o.beta_dec < 1) ||
         !(o.beta_inc >= 1) || o.n_inc < 1 || o.max_newton < 0 || o.max_steps < 0 || o.max_refine < 0 ||
-        o.steps_per_launch < 0 || o.tracks_per_item < 0)
+        o.steps_per_launch < -1 || o.tracks_per_item < 0)
         return fail(HC_E_INVALID, "opts: step-control values out of range");
+    if (o.table_layout != HC_LAYOUT_AUTO && o.table_layout != HC_LAYOUT_DENSE && o.table_layout != HC_LAYOUT_TERMS)
+        return fail(HC_E_INVALID, "opts.table_layout = %d", o.table_layout);
     if (o.lanes_per_path != 0 && o.lanes_per_path != 1 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
         o.lanes_per_path != 16)
         return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4, 8 or 16)", o.lanes_per_path);
@@ -453,15 +528,53 @@ static void put(std::vector<unsigned char> &k, const T &v)
     k.insert(k.end(), b, b + sizeof(T));
 }
 
-static std::vector<unsigned char> tune_key(const hc_system *s, int precision, int n_start, int n_inst)
+// Autotuner key: the workload's shape, not the system's address (a system loaded
+// later with the same shape takes the same choice; a freed one leaves nothing
+// behind that could mislead a new one).
+static std::string tune_key(const hc_ctx *c, const hc_system *s, int precision, int n_start, int n_inst)
 {
-    std::vector<unsigned char> k;
-    put(k, s);
-    put(k, precision);
-    put(k, n_start);
-    put(k, n_inst);
-    return k;
+    char b[256];
+    std::snprintf(b, sizeof b, "%s layout=%d kind=%d n=%d terms=%d slots=%d maxdeg=%d deg2=%x tk=%d prec=%d "
+                  "n_start=%d n_inst=%d", c->arch.c_str(), s->layout, s->kind, s->n, s->n_terms, s->T, s->max_deg,
+                  s->deg2, s->tk, precision, n_start, n_inst);
+    return b;
 }
+
+// Applies a tuned choice for this workload when the call leaves the work
+// decomposition to the library (tracks_per_item = lanes_per_path = 0; a
+// steps_per_launch of -1 takes the tuned value too, else 0).  May switch the
+// system to its copy in the tuned table layout.
+static hc_status apply_tuning(hc_ctx *c, const hc_system *&s, hc_opts &o, int n_start, int n_inst)
+{
+    if (o.lanes_per_path == 0 && o.tracks_per_item == 0 && o.table_layout == HC_LAYOUT_AUTO) {
+        auto it = c->tune.find(tune_key(c, s, o.precision, n_start, n_inst));
+        if (it != c->tune.end()) {
+            const TuneChoice &tc = it->second;
+            o.table_layout = tc.layout;
+            o.lanes_per_path = tc.lanes;
+            o.tracks_per_item = tc.tpi;
+            if (o.steps_per_launch < 0) o.steps_per_launch = tc.spl;
+        }
+    }
+    if (o.steps_per_launch < 0) o.steps_per_launch = 0;
+    if (o.table_layout != HC_LAYOUT_AUTO && o.table_layout != s->layout) {
+        const hc_system *t = alt_layout(c, s);
+        if (!t || t->layout != o.table_layout)
+            return fail(HC_E_UNSUPPORTED, "opts.table_layout = %d cannot hold this system (n = %d, degree %d)",
+                        o.table_layout, s->n, s->max_deg);
+        s = t;
+    }
+    return HC_OK;
+}
+
+// Mixed mode with the crossing check on instances above kDedupMax paths: the
+// check keeps its projections in the workspace (16 bytes per path).
+static bool mixed_check_big(const hc_opts &o, int n_start)
+{
+    return o.precision == HC_MIXED && o.crossing_check && n_start > kDedupMax;
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                                    const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
@@ -475,14 +588,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     else hc_default_opts(&o);
     hc_status rc = check_opts(o);
     if (rc != HC_OK) return rc;
-    if (o.lanes_per_path == 0 && o.tracks_per_item == 0) {
-        const std::vector<unsigned char> k = tune_key(s, o.precision, n_start, n_inst);
-        for (auto &e : c->tune)
-            if (e.first == k) {
-                o.lanes_per_path = e.second.first;
-                o.tracks_per_item = e.second.second;
-            }
-    }
+    rc = apply_tuning(c, s, o, n_start, n_inst);
+    if (rc != HC_OK) return rc;
     const bool param = s->kind == HC_PARAMETER;
     if (!param && !start && n_start > s->bezout)
         return fail(HC_E_INVALID, "hc_track: n_start = %d exceeds the Bezout number %lld", n_start,
@@ -499,18 +606,25 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const bool mixed = o.precision == HC_MIXED;
     const int n_slots = n * T;
 
-    // workspace: SoA state, then kernel tables
+    // workspace: SoA state (+ the crossing check's projections of instances
+    // above kDedupMax paths), then kernel tables
     const size_t st_doubles = (size_t)total * (2 * n + 2);
     const size_t st_ints = (size_t)total * 6;
-    HIP_TRY(c->state.ensure(st_doubles * 8 + st_ints * 4));
+    const bool big_check = mixed_check_big(o, n_start);
+    const size_t proj_off = al256(st_doubles * 8 + st_ints * 4);
+    const size_t state_bytes = big_check ? proj_off + (size_t)total * 16 : st_doubles * 8 + st_ints * 4;
     // tables: n_inst target instances (+ the start instance(s) of a parameter homotopy)
     const bool pis = o.per_instance_start != 0;
     const int n_tab = n_inst + (param ? (pis ? n_inst : 1) : 0);
     const size_t coef64 = (size_t)n_tab * n_slots * 2 * sizeof(double);
     const size_t coef32 = mixed ? (size_t)n_tab * n_slots * 2 * sizeof(float) : 0;
+    HIP_TRY(c->state.ensure(state_bytes));
     HIP_TRY(c->coef.ensure(coef64 + coef32));
     HIP_TRY(c->counter.ensure(64));
-    unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(static_cast<char *>(c->counter.p) + 16);
+    char *state_p = static_cast<char *>(c->state.p);
+    char *coef_p = static_cast<char *>(c->coef.p);
+    char *counter_p = static_cast<char *>(c->counter.p);
+    unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(counter_p + 16);
     const bool prof = c->profiling;
     if (prof) {
         for (hipEvent_t &e : c->ev)
@@ -522,7 +636,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     }
 
     TrackState S;
-    double *dp = static_cast<double *>(c->state.p);
+    double *dp = reinterpret_cast<double *>(state_p);
     S.xr = dp;
     S.xi = dp + (size_t)total * n;
     S.t = dp + (size_t)total * 2 * n;
@@ -534,8 +648,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     S.nits = ip + 3 * total;
     S.status = ip + 4 * total;
     S.escal = ip + 5 * total;
-    double *tab64 = static_cast<double *>(c->coef.p);
-    float *tab32 = mixed ? reinterpret_cast<float *>(static_cast<char *>(c->coef.p) + coef64) : nullptr;
+    double *tab64 = reinterpret_cast<double *>(coef_p);
+    float *tab32 = mixed ? reinterpret_cast<float *>(coef_p + coef64) : nullptr;
 
     PrepArgs pa;
     pa.n = n;
@@ -612,8 +726,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     ta.max_newton = o.max_newton;
     ta.max_steps = o.max_steps;
     ta.s = S;
-    ta.n_suspended = static_cast<unsigned *>(c->counter.p);
-    ta.head = reinterpret_cast<unsigned *>(static_cast<char *>(c->counter.p) + 32);
+    ta.n_suspended = reinterpret_cast<unsigned *>(counter_p);
+    ta.head = reinterpret_cast<unsigned *>(counter_p + 32);
     ta.vars = s->d_vars;
     ta.n_tslots = s->T;
     ta.sdeg = sdeg_of(s);
@@ -707,6 +821,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         da.endpoints = reinterpret_cast<const double *>(endpoints);
         da.status = status;
         da.s = S;
+        da.proj = big_check ? reinterpret_cast<double *>(state_p + proj_off) : nullptr;
         HIP_TRY(launch_dedup(da, st));
         InitArgs ir = ia;
         ir.retrack = 1;
@@ -822,60 +937,128 @@ hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_
     hc_opts o;
     if (opts) o = *opts;
     else hc_default_opts(&o);
+    hc_status rc = check_opts(o);
+    if (rc != HC_OK) return rc;
+    const bool tune_spl = o.steps_per_launch < 0;
     o.use_graph = 0;
-    o.steps_per_launch = 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(c->device));
-    // candidates: lanes per path x paths per lane group (or per lane)
-    std::vector<std::pair<int, int>> cand;
-    if (s->n >= 2) {
-        const int g = lanes_for(s);
-        for (int per_group : {1, 2, 4, 8}) cand.push_back({g, per_group * (64 / g)});
+    // candidates: table layout (the system's, and the other one where it can hold
+    // the system) x lanes per path x paths per work item (x steps per launch
+    // when asked for)
+    struct Cand {
+        const hc_system *sys;
+        TuneChoice ch;
+    };
+    std::vector<Cand> cand;
+    const hc_system *layouts[2] = {s, alt_layout(c, s)};
+    for (const hc_system *ls : layouts) {
+        if (!ls) continue;
+        std::vector<std::pair<int, int>> lt;  // (lanes, paths per item)
+        if (ls->n >= 2) {
+            const int g = lanes_for(ls);
+            for (int per_group : {1, 2, 4}) lt.push_back({g, per_group * (64 / g)});
+        }
+        if (ls->kind == HC_TOTAL_DEGREE && ls->layout == HC_LAYOUT_DENSE)
+            for (int tpi : {64, 256}) lt.push_back({1, tpi});
+        for (auto &x : lt)
+            for (int spl : {0, 64, 512}) {
+                if (spl && !tune_spl) continue;
+                Cand cd;
+                cd.sys = ls;
+                cd.ch.layout = ls->layout;
+                cd.ch.lanes = x.first;
+                cd.ch.tpi = std::max(1, std::min(x.second, std::max(n_start, 1)));
+                cd.ch.spl = spl;
+                cand.push_back(cd);
+            }
     }
-    if (s->kind == HC_TOTAL_DEGREE && s->layout == HC_LAYOUT_DENSE)
-        for (int tpi : {64, 128, 256}) cand.push_back({1, tpi});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best_ms = 0.0f;
-    std::pair<int, int> pick = {0, 0};
-    hc_status rc = HC_OK;
-    for (auto &cd : cand) {
+    TuneChoice pick;
+    for (const Cand &cd : cand) {
         hc_opts t = o;
-        t.lanes_per_path = cd.first;
-        t.tracks_per_item = std::max(1, std::min(cd.second, std::max(n_start, 1)));
+        t.lanes_per_path = cd.ch.lanes;
+        t.tracks_per_item = cd.ch.tpi;
+        t.steps_per_launch = cd.ch.spl;
+        t.table_layout = cd.ch.layout;
         rc = track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, &t, endpoints, status,
                                info, st);
         if (rc != HC_OK) break;
-        HIP_TRY(hipEventRecord(e0, st));
-        rc = track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, &t, endpoints, status,
-                               info, st);
-        if (rc != HC_OK) break;
-        HIP_TRY(hipEventRecord(e1, st));
-        HIP_TRY(hipEventSynchronize(e1));
+        hipError_t e = hipEventRecord(e0, st);
+        if (e == hipSuccess)
+            rc = track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, &t, endpoints,
+                                   status, info, st);
+        if (e == hipSuccess && rc == HC_OK) e = hipEventRecord(e1, st);
+        if (e == hipSuccess && rc == HC_OK) e = hipEventSynchronize(e1);
         float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (pick.first == 0 || ms < best_ms) {
+        if (e == hipSuccess && rc == HC_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) rc = fail(HC_E_DEVICE, "hc_autotune: %s", hipGetErrorString(e));
+        if (rc != HC_OK) break;
+        if (pick.lanes == 0 || ms < best_ms) {
             best_ms = ms;
-            pick = {cd.first, t.tracks_per_item};
+            pick = cd.ch;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != HC_OK) return rc;
-    if (pick.first == 0) return fail(HC_E_UNSUPPORTED, "hc_autotune: no candidate applies to this system");
-    const std::vector<unsigned char> k = tune_key(s, o.precision, n_start, n_inst);
-    bool found = false;
-    for (auto &e : c->tune)
-        if (e.first == k) {
-            e.second = pick;
-            found = true;
-        }
-    if (!found) c->tune.push_back({k, pick});
+    if (pick.lanes == 0) return fail(HC_E_UNSUPPORTED, "hc_autotune: no candidate applies to this system");
+    c->tune[tune_key(c, s, o.precision, n_start, n_inst)] = pick;
+    if (!c->tune_file.empty() && hc_tune_save(c, c->tune_file.c_str()) != HC_OK) return HC_E_INVALID;
     *best = o;
     if (opts) best->use_graph = opts->use_graph;
-    best->lanes_per_path = pick.first;
-    best->tracks_per_item = pick.second;
+    best->lanes_per_path = pick.lanes;
+    best->tracks_per_item = pick.tpi;
+    best->steps_per_launch = pick.spl;
+    best->table_layout = pick.layout;
+    return HC_OK;
+}
+
+hc_status hc_tune_save(hc_ctx *c, const char *path)
+{
+    clear_error();
+    if (!c || !path) return fail(HC_E_INVALID, "hc_tune_save: NULL argument");
+    std::ofstream f(path, std::ios::trunc);
+    if (!f) return fail(HC_E_INVALID, "hc_tune_save: cannot write %s", path);
+    f << "# homotopy tracker autotuner cache: key -> layout lanes_per_path tracks_per_item steps_per_launch\n";
+    for (const auto &e : c->tune)
+        f << e.first << " -> " << e.second.layout << " " << e.second.lanes << " " << e.second.tpi << " "
+          << e.second.spl << "\n";
+    f.flush();
+    if (!f) return fail(HC_E_INVALID, "hc_tune_save: write to %s failed", path);
+    return HC_OK;
+}
+
+hc_status hc_tune_load(hc_ctx *c, const char *path, int32_t *n_loaded)
+{
+    clear_error();
+    if (!c || !path) return fail(HC_E_INVALID, "hc_tune_load: NULL argument");
+    std::ifstream f(path);
+    if (!f) return fail(HC_E_INVALID, "hc_tune_load: cannot read %s", path);
+    std::map<std::string, TuneChoice> got;
+    std::string line;
+    int lineno = 0;
+    while (std::getline(f, line)) {
+        lineno++;
+        if (line.empty() || line[0] == '#') continue;
+        const size_t arrow = line.find(" -> ");
+        TuneChoice tc;
+        if (arrow != std::string::npos) {
+            std::istringstream v(line.substr(arrow + 4));
+            if ((v >> tc.layout >> tc.lanes >> tc.tpi >> tc.spl) &&
+                (tc.layout == HC_LAYOUT_DENSE || tc.layout == HC_LAYOUT_TERMS) && tc.lanes >= 1 && tc.tpi >= 1 &&
+                tc.spl >= 0) {
+                got[line.substr(0, arrow)] = tc;
+                continue;
+            }
+        }
+        return fail(HC_E_INVALID, "hc_tune_load: %s line %d is not 'key -> layout lanes tpi spl'", path, lineno);
+    }
+    for (auto &e : got) c->tune[e.first] = e.second;
+    if (n_loaded) *n_loaded = (int32_t)got.size();
     return HC_OK;
 }
 
@@ -937,21 +1120,15 @@ hc_status hc_track(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n
     return HC_OK;
 }
 
-hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts_in,
-                                void *stream)
+}  // extern "C"
+
+// The batch launch sequence.  upload = false (graph capture): the job blob is
+// already on the device from the eager call with the same arguments, so only
+// the kernels are enqueued.
+static hc_status track_batch_impl(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, const hc_opts &o, hipStream_t st,
+                                  bool upload)
 {
-    clear_error();
-    if (!c || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(HC_E_INVALID, "hc_track_batch_device: bad arguments");
-    hc_opts o;
-    if (opts_in) o = *opts_in;
-    else hc_default_opts(&o);
-    hc_status rc = check_opts(o);
-    if (rc != HC_OK) return rc;
-    if (o.steps_per_launch != 0 || o.lanes_per_path == 1)
-        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: needs steps_per_launch = 0 and lanes_per_path 0/4/8");
-    if (o.per_instance_start)
-        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: per_instance_start is not available in a batch");
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    hc_status rc = HC_OK;
     const bool mixed = o.precision == HC_MIXED;
 
     // per-job sizes and workspace offsets
@@ -961,8 +1138,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         long long total;
         int n, T, n_slots, n_tab, tpi;
         bool param;
-        size_t st_off, tab64_off, tab32_off;
-            InitArgs init;
+        size_t st_off, proj_off, tab64_off, tab32_off;
+        InitArgs init;
     };
     std::vector<Plan> plan;
     size_t st_bytes = 0, tab_bytes = 0;
@@ -995,6 +1172,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         p.tpi = choose_tracks_per_item(o, j.n_start, lanes_for(s));
         p.st_off = st_bytes;
         st_bytes += al((size_t)p.total * ((2 * p.n + 2) * 8 + 6 * 4));
+        p.proj_off = st_bytes;
+        if (mixed_check_big(o, j.n_start)) st_bytes += al((size_t)p.total * 16);
         p.tab64_off = tab_bytes;
         tab_bytes += al((size_t)p.n_tab * p.n_slots * 16);
         p.tab32_off = tab_bytes;
@@ -1139,7 +1318,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     // refinement, crossing-check and re-tracking arguments per job; refinement
     // launches once per dense n and once for the term lists
     std::vector<RefineArgs> refs[kRefSlots];  // [n] dense, [kMaxN + 1 + kind] term lists
-    std::vector<DedupArgs> dedups;
+    std::vector<DedupArgs> dedups, big_dedups;  // big: instances above kDedupMax paths
     std::vector<InitArgs> retracks;
     long long ref_items[kRefSlots] = {}, ref_total[kRefSlots] = {};
     int max_inst = 0, max_start = 0;
@@ -1179,6 +1358,11 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         da.endpoints = reinterpret_cast<const double *>(p.j->endpoints);
         da.status = p.j->status;
         da.s = ta.s;
+        da.proj = nullptr;
+        if (mixed_check_big(o, p.j->n_start)) {
+            da.proj = reinterpret_cast<double *>(static_cast<char *>(c->state.p) + p.proj_off);
+            big_dedups.push_back(da);
+        }
         dedups.push_back(da);
         max_inst = std::max(max_inst, p.j->n_inst);
         max_start = std::max(max_start, p.j->n_start);
@@ -1216,7 +1400,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     for (int rk = 0; rk < kRefSlots; rk++) put_arr(o_ref[rk], refs[rk].data(), refs[rk].size() * sizeof(RefineArgs));
     HIP_TRY(c->queue.ensure(off));
     char *qb = static_cast<char *>(c->queue.p);
-    HIP_TRY(hipMemcpyAsync(qb, c->h_blob.data(), o_heads, hipMemcpyHostToDevice, st));
+    if (upload) HIP_TRY(hipMemcpyAsync(qb, c->h_blob.data(), o_heads, hipMemcpyHostToDevice, st));
     TrackArgs *d_jobs = reinterpret_cast<TrackArgs *>(qb + o_jobs);
     QueueItem *d_items = reinterpret_cast<QueueItem *>(qb + o_items);
     unsigned *heads = reinterpret_cast<unsigned *>(qb + o_heads);
@@ -1263,6 +1447,7 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         // refinement of the re-tracked paths
         HIP_TRY(launch_dedup_many(reinterpret_cast<const DedupArgs *>(qb + o_dedup), (int)dedups.size(), max_inst,
                                   max_start, st));
+        for (const DedupArgs &da : big_dedups) HIP_TRY(launch_dedup_big(da, st));
         HIP_TRY(launch_init_many(reinterpret_cast<const InitArgs *>(qb + o_retr), (int)retracks.size(), max_total,
                                  st));
         rc = run_pass(false);
@@ -1270,6 +1455,71 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
         rc = refine_all();
         if (rc != HC_OK) return rc;
     }
+    return HC_OK;
+}
+
+extern "C" {
+
+hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, const hc_opts *opts_in,
+                                void *stream)
+{
+    clear_error();
+    if (!c || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(HC_E_INVALID, "hc_track_batch_device: bad arguments");
+    hc_opts o;
+    if (opts_in) o = *opts_in;
+    else hc_default_opts(&o);
+    hc_status rc = check_opts(o);
+    if (rc != HC_OK) return rc;
+    if (o.steps_per_launch > 0 || o.lanes_per_path == 1)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: needs steps_per_launch 0 (or -1) and lanes_per_path "
+                                      "0/4/8");
+    o.steps_per_launch = 0;
+    if (o.per_instance_start)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: per_instance_start is not available in a batch");
+    if (o.table_layout != HC_LAYOUT_AUTO)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: table_layout must be 0 (each job's own)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool graph = o.use_graph && st != nullptr && !c->profiling;
+    if (!graph) return track_batch_impl(c, n_jobs, jobs, o, st, true);
+    auto key = [&]() {
+        std::vector<unsigned char> k;
+        put(k, n_jobs);
+        for (int j = 0; j < n_jobs; j++) put(k, jobs[j]);
+        put(k, o);
+        put(k, st);
+        put(k, c->state.moves);
+        put(k, c->coef.moves);
+        put(k, c->counter.moves);
+        put(k, c->queue.moves);
+        return k;
+    };
+    if (c->bgraph_valid && key() == c->bgraph_key) {
+        HIP_TRY(hipGraphLaunch(c->bgraph_exec, st));
+        return HC_OK;
+    }
+    // first call with these arguments: run it eagerly (sizes the workspace and
+    // uploads the job blob), then record its kernels for replays
+    rc = track_batch_impl(c, n_jobs, jobs, o, st, true);
+    if (rc != HC_OK) return rc;
+    c->bgraph_valid = false;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    rc = track_batch_impl(c, n_jobs, jobs, o, st, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != HC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(HC_E_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (c->bgraph_exec) {
+        (void)hipGraphExecDestroy(c->bgraph_exec);
+        c->bgraph_exec = nullptr;
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->bgraph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(HC_E_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    c->bgraph_key = key();
+    c->bgraph_valid = true;
     return HC_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -78,6 +79,16 @@ struct hc_system {
     int max_deg = 0;          // largest term degree
     int *d_sdeg = nullptr;    // general-degree kinds: [T] largest degree of each slot
     int *d_eqdeg = nullptr;   // general-degree kinds: [n] equation degrees
+    // the description as loaded: the autotuner loads the other table layout from it
+    std::vector<int> h_term_eq, h_term_exp, h_rowptr, h_col;
+    std::vector<hc_c64> h_const, h_val;
+    hc_system *alt = nullptr; // the same family in the other table layout (autotuner), owned here
+};
+
+// An autotuner choice: table layout, lanes per path, paths per work item and
+// steps per launch (0 = to the end).
+struct TuneChoice {
+    int layout = 0, lanes = 0, tpi = 0, spl = 0;
 };
 
 struct hc_ctx {
@@ -96,8 +107,16 @@ struct hc_ctx {
     bool graph_valid = false;
     std::vector<unsigned char> graph_key;
     hipGraphExec_t graph_exec = nullptr;
-    // autotuner choices: key -> (lanes_per_path, tracks_per_item)
-    std::vector<std::pair<std::vector<unsigned char>, std::pair<int, int>>> tune;
+    // hipGraph of the last hc_track_batch_device call with use_graph
+    bool bgraph_valid = false;
+    std::vector<unsigned char> bgraph_key;
+    hipGraphExec_t bgraph_exec = nullptr;
+    // autotuner choices by workload shape (a text key that names the device
+    // architecture, the system's table layout, kind, sizes and degrees, the
+    // precision and the batch sizes); persisted by hc_tune_save / hc_tune_load
+    std::string arch;
+    std::map<std::string, TuneChoice> tune;
+    std::string tune_file;   // HC_TUNE_CACHE at creation: loaded then, rewritten by hc_autotune
     // profiling: events bracketing prep | init | FP32 pass | FP64 pass | refine
     bool profiling = false;
     bool profiled_call = false;

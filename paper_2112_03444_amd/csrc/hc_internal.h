@@ -36,7 +36,9 @@ __host__ __device__ inline int steps_used(int steps, int rejects, int escal)
     return steps + rejects - (escal > 0 ? escal - 1 : 0);
 }
 
-constexpr int kDedupMax = 8192;  // largest n_start the crossing check handles
+// Largest n_start whose crossing check keeps the instance's projections in LDS;
+// larger instances go through global memory (launch_dedup_big).
+constexpr int kDedupMax = 8192;
 
 // Mixed precision on the group trackers: 1 = a failed FP32 path goes on in FP64
 // inside the same launch; 0 = it goes back to RUNNING and a second (FP64) launch
@@ -95,6 +97,7 @@ struct DedupArgs {
     const double *endpoints;  // [total][n][2]
     const int *status;        // [total] final statuses
     TrackState s;
+    double *proj;             // [total][2] workspace of instances above kDedupMax paths, else null
 };
 
 struct TrackArgs {
@@ -207,9 +210,13 @@ template <int TK>
 hipError_t launch_refine_terms_k(const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st);
 hipError_t launch_refine(int n, const RefineArgs &a, hipStream_t st);
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st);
+// The crossing check of one job whose instances have more than kDedupMax paths
+// (a.proj must hold a.total complex values).
+hipError_t launch_dedup_big(const DedupArgs &a, hipStream_t st);
 // Batch API: one launch per step over many jobs (argument arrays in device memory).
 hipError_t launch_prep_many(const PrepArgs *a, int count, long long max_work, hipStream_t st);
 hipError_t launch_init_many(const InitArgs *a, int count, long long max_total, hipStream_t st);
+// Jobs above kDedupMax paths per instance are skipped: launch_dedup_big each.
 hipError_t launch_dedup_many(const DedupArgs *a, int count, int max_inst, int max_start, hipStream_t st);
 // max_items: the largest n_inst * ceil(n_start / 64) of the jobs (n = 1), max_total
 // the largest path count (2 <= n <= 8)

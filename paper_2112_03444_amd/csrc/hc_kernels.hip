@@ -450,49 +450,60 @@ struct k_dedup_tag {
     static constexpr int cap = C;
 };
 
+// A complex projection of a SUCCESS endpoint (NaN for any other status): the
+// cheap first comparison of the crossing check.
+__device__ __forceinline__ cx<double> dedup_proj(const DedupArgs &a, long long g)
+{
+    cx<double> p = {NAN, NAN};
+    if (a.status[g] == HC_T_SUCCESS) {
+        p = {0.0, 0.0};
+        for (int j = 0; j < a.n; j++) {
+            const cx<double> w = {cos(1.3 * j + 0.4), sin(2.1 * j + 0.9)};  // fixed generic weights
+            p = cfma(w, cx<double>{a.endpoints[(g * a.n + j) * 2], a.endpoints[(g * a.n + j) * 2 + 1]}, p);
+        }
+    }
+    return p;
+}
+
+// Full comparison of two endpoints whose projections are close: relative
+// inf-norm distance within a.tol.
+__device__ __forceinline__ bool dedup_same(const DedupArgs &a, long long g, long long h)
+{
+    double dmax = 0.0, cmax = 0.0;
+    for (int j = 0; j < a.n; j++) {
+        const double xr = a.endpoints[(g * a.n + j) * 2], xi = a.endpoints[(g * a.n + j) * 2 + 1];
+        const double yr = a.endpoints[(h * a.n + j) * 2], yi = a.endpoints[(h * a.n + j) * 2 + 1];
+        dmax = fmax(dmax, sqrt((xr - yr) * (xr - yr) + (xi - yi) * (xi - yi)));
+        cmax = fmax(cmax, sqrt(yr * yr + yi * yi));
+    }
+    return dmax <= a.tol * fmax(1.0, cmax);
+}
+
+__device__ __forceinline__ bool dedup_near(cx<double> pb, cx<double> pc)
+{
+    return fabs(pc.re - pb.re) + fabs(pc.im - pb.im) <= 1e-6 * (1.0 + sqrt(abs2(pb)));
+}
+
 // CAP: LDS entries of the block (the launcher picks the smallest of 64, 1024 and
 // kDedupMax that holds every instance it covers, so small instances do not tie
-// up 128 KB of LDS per block); instances above kDedupMax are not checked.
+// up 128 KB of LDS per block).  Instances above CAP paths are left to
+// k_dedup_big (this body returns without touching them).
 template <int CAP>
 __device__ __forceinline__ void dedup_body(const DedupArgs &a, int inst)
 {
     __shared__ cx<double> proj[CAP];
-    if (inst >= a.n_inst) return;
+    if (inst >= a.n_inst || a.n_start > CAP) return;
     const long long g0 = (long long)inst * a.n_start;
     const TrackState S = a.s;
-    const bool check = a.n_start <= CAP;
-    for (int b = threadIdx.x; check && b < a.n_start; b += blockDim.x) {
-        const long long g = g0 + b;
-        cx<double> p = {NAN, NAN};
-        if (a.status[g] == HC_T_SUCCESS) {
-            p = {0.0, 0.0};
-            for (int j = 0; j < a.n; j++) {
-                const cx<double> w = {cos(1.3 * j + 0.4), sin(2.1 * j + 0.9)};  // fixed generic weights
-                p = cfma(w, cx<double>{a.endpoints[(g * a.n + j) * 2], a.endpoints[(g * a.n + j) * 2 + 1]}, p);
-            }
-        }
-        proj[b] = p;
-    }
+    for (int b = threadIdx.x; b < a.n_start; b += blockDim.x) proj[b] = dedup_proj(a, g0 + b);
     __syncthreads();
     for (int b = threadIdx.x; b < a.n_start; b += blockDim.x) {
         const long long g = g0 + b;
         bool dup = false;
-        if (check && a.status[g] == HC_T_SUCCESS) {
+        if (a.status[g] == HC_T_SUCCESS) {
             const cx<double> pb = proj[b];
-            const double pre = 1e-6 * (1.0 + sqrt(abs2(pb)));
-            for (int c = 0; c < a.n_start && !dup; c++) {
-                const cx<double> pc = proj[c];
-                if (c == b || !(fabs(pc.re - pb.re) + fabs(pc.im - pb.im) <= pre)) continue;
-                const long long h = g0 + c;
-                double dmax = 0.0, cmax = 0.0;
-                for (int j = 0; j < a.n; j++) {
-                    const double xr = a.endpoints[(g * a.n + j) * 2], xi = a.endpoints[(g * a.n + j) * 2 + 1];
-                    const double yr = a.endpoints[(h * a.n + j) * 2], yi = a.endpoints[(h * a.n + j) * 2 + 1];
-                    dmax = fmax(dmax, sqrt((xr - yr) * (xr - yr) + (xi - yi) * (xi - yi)));
-                    cmax = fmax(cmax, sqrt(yr * yr + yi * yi));
-                }
-                dup = dmax <= a.tol * fmax(1.0, cmax);
-            }
+            for (int c = 0; c < a.n_start && !dup; c++)
+                if (c != b && dedup_near(pb, proj[c])) dup = dedup_same(a, g, g0 + c);
         }
         S.status[g] = dup ? kRetrack : kDone;
     }
@@ -507,8 +518,44 @@ __global__ __launch_bounds__(256) void k_dedup_many(const DedupArgs *a)
     dedup_body<CAP>(a[blockIdx.y], blockIdx.x);
 }
 
+// Instances with more than kDedupMax paths: every path's projection goes to
+// a.proj in global memory (k_dedup_proj, one thread per path), then each thread
+// of k_dedup_big compares its path with all of its instance's projections,
+// staged through LDS one tile at a time (one block per 256 paths of an
+// instance, the instance's blocks consecutive).
+constexpr int kDedupTile = 1024;
+
+__global__ __launch_bounds__(256) void k_dedup_proj(const DedupArgs a)
+{
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < a.total) reinterpret_cast<cx<double> *>(a.proj)[g] = dedup_proj(a, g);
+}
+
+__global__ __launch_bounds__(256) void k_dedup_big(const DedupArgs a)
+{
+    __shared__ cx<double> tile[kDedupTile];
+    const int nb = (a.n_start + 255) / 256;  // path blocks per instance
+    const int b = (int)(blockIdx.x % nb) * blockDim.x + threadIdx.x;
+    const long long g0 = (long long)(blockIdx.x / nb) * a.n_start;
+    const long long g = g0 + b;
+    const bool mine = b < a.n_start && a.status[g] == HC_T_SUCCESS;
+    const cx<double> *proj = reinterpret_cast<const cx<double> *>(a.proj);
+    const cx<double> pb = mine ? proj[g] : cx<double>{NAN, NAN};
+    bool dup = false;
+    for (int c0 = 0; c0 < a.n_start; c0 += kDedupTile) {
+        const int m = min(kDedupTile, a.n_start - c0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < m; j += blockDim.x) tile[j] = proj[g0 + c0 + j];
+        __syncthreads();
+        for (int j = 0; mine && !dup && j < m; j++)
+            if (c0 + j != b && dedup_near(pb, tile[j])) dup = dedup_same(a, g, g0 + c0 + j);
+    }
+    if (b < a.n_start) a.s.status[g] = dup ? kRetrack : kDone;
+}
+
 // The block's LDS capacity and size for instances of up to max_start paths
-// (above kDedupMax: the largest block; those instances are left unchecked).
+// (above kDedupMax: the largest block, which leaves those instances to
+// k_dedup_big).
 template <typename L>
 static hipError_t dedup_dispatch(int max_start, L launch)
 {
@@ -517,9 +564,20 @@ static hipError_t dedup_dispatch(int max_start, L launch)
     return launch(k_dedup_tag<kDedupMax>{}, 256);
 }
 
+hipError_t launch_dedup_big(const DedupArgs &a, hipStream_t st)
+{
+    if (a.total == 0 || a.n_inst == 0) return hipSuccess;
+    if (!a.proj) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dedup_proj, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, st, a);
+    const long long blocks = (long long)((a.n_start + 255) / 256) * a.n_inst;
+    hipLaunchKernelGGL(k_dedup_big, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_dedup(const DedupArgs &a, hipStream_t st)
 {
     if (a.total == 0 || a.n_inst == 0) return hipSuccess;
+    if (a.n_start > kDedupMax) return launch_dedup_big(a, st);
     return dedup_dispatch(a.n_start, [&](auto tag, int threads) {
         hipLaunchKernelGGL(k_dedup<decltype(tag)::cap>, dim3((unsigned)a.n_inst), dim3(threads), 0, st, a);
         return hipGetLastError();

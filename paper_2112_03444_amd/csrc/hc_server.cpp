@@ -25,9 +25,23 @@ using clk = std::chrono::steady_clock;
 
 namespace {
 
+}  // namespace
+
+// A start set kept on the device for the server's lifetime: requests that name
+// it track from these points (and start parameters) without copying them.
+struct hc_start_set {
+    const hc_system *sys = nullptr;
+    int32_t n_start = 0;
+    hc_c64 *d_start = nullptr;   // [n_start][n]
+    hc_c64 *d_pstart = nullptr;  // [n_params] or null
+};
+
+namespace {
+
 struct Request {
     int64_t ticket = 0;
     const hc_system *sys = nullptr;
+    const hc_start_set *set = nullptr;  // resident start points, or null (copied below)
     int n = 0, n_params = 0, n_start = 0, n_inst = 0;
     std::vector<hc_c64> start, p_start, p_target, gamma;  // copies made at submission
     hc_c64 *endpoints = nullptr;
@@ -98,17 +112,19 @@ struct hc_server {
     clk::time_point t_stats;
     double busy_s = 0.0;
     std::thread dispatcher, completer;
+    std::vector<hc_start_set *> start_sets;
 };
 
 namespace {
 
-size_t footprint(const hc_system *s, int n_start, int n_inst, bool with_info)
+size_t footprint(const hc_system *s, int n_start, int n_inst, bool with_info, bool resident_start)
 {
     const size_t total = (size_t)n_start * n_inst;
     const size_t state = total * (16 * (size_t)s->n + 28);
     const size_t tables = (size_t)(n_inst + 1) * s->n * s->T * 24;
     const size_t io = total * (16 * (size_t)s->n + 4 + (with_info ? 32 : 0)) +
-                      ((size_t)n_inst + 1) * (s->n_params + 1) * 16 + (size_t)n_start * s->n * 16;
+                      ((size_t)n_inst + 1) * (s->n_params + 1) * 16 +
+                      (resident_start ? 0 : (size_t)n_start * s->n * 16);
     return state + tables + io + 4096;
 }
 
@@ -159,10 +175,12 @@ hc_status launch_batch(hc_server *sv, Slot &sl)
     for (Request *r : sl.reqs) {
         hc_job j;
         j.sys = r->sys;
-        j.start = r->start.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_start);
+        j.start = r->set ? r->set->d_start
+                         : r->start.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_start);
         j.n_start = r->n_start;
         j.n_inst = r->n_inst;
-        j.p_start = r->p_start.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_pstart);
+        j.p_start = r->set ? r->set->d_pstart
+                           : r->p_start.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_pstart);
         j.p_target = r->p_target.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_ptarget);
         j.gamma = r->gamma.empty() ? nullptr : reinterpret_cast<const hc_c64 *>(dev + r->o_gamma);
         j.endpoints = reinterpret_cast<hc_c64 *>(dev + sl.out_base + r->o_ep);
@@ -372,18 +390,32 @@ hc_status hc_server_submit(hc_server *sv, const hc_request *rq, int64_t *ticket)
     if (s->n < 2) return fail(HC_E_UNSUPPORTED, "hc_server_submit: n = 1 is not served");
     if (rq->n_start < 0 || rq->n_inst < 0) return fail(HC_E_INVALID, "hc_server_submit: negative size");
     const bool param = s->kind == HC_PARAMETER;
+    const hc_start_set *set = rq->start_set;
+    if (set) {
+        bool known;
+        {
+            std::lock_guard<std::mutex> lk(sv->m);
+            known = std::find(sv->start_sets.begin(), sv->start_sets.end(), set) != sv->start_sets.end();
+        }
+        if (!known) return fail(HC_E_INVALID, "hc_server_submit: start_set was not added to this server");
+        if (set->sys != s) return fail(HC_E_INVALID, "hc_server_submit: start_set belongs to another system");
+        if (rq->start || rq->p_start || rq->n_start != set->n_start)
+            return fail(HC_E_INVALID, "hc_server_submit: with start_set, start and p_start are NULL and n_start is "
+                                      "the set's (%d)", set->n_start);
+    }
     const size_t total = (size_t)rq->n_start * rq->n_inst;
     if (total > 0) {
         if (!rq->endpoints || !rq->status || (!rq->p_target && s->n_params > 0))
             return fail(HC_E_INVALID, "hc_server_submit: NULL buffer");
-        if (!param && !rq->start && rq->n_start > s->bezout)
+        if (!param && !rq->start && !set && rq->n_start > s->bezout)
             return fail(HC_E_INVALID, "hc_server_submit: n_start exceeds the Bezout number");
-        if (param && (!rq->start || (!rq->p_start && s->n_params > 0)))
+        if (param && !set && (!rq->start || (!rq->p_start && s->n_params > 0)))
             return fail(HC_E_INVALID, "hc_server_submit: a parameter homotopy needs start points and p_start");
     }
     Request *r = new (std::nothrow) Request;
     if (!r) return fail(HC_E_OOM, "hc_server_submit: out of host memory");
     r->sys = s;
+    r->set = set;
     r->n = s->n;
     r->n_params = s->n_params;
     r->n_start = rq->n_start;
@@ -395,7 +427,7 @@ hc_status hc_server_submit(hc_server *sv, const hc_request *rq, int64_t *ticket)
     r->endpoints = rq->endpoints;
     r->status = rq->status;
     r->info = rq->info;
-    r->bytes = footprint(s, rq->n_start, rq->n_inst, rq->info != nullptr);
+    r->bytes = footprint(s, rq->n_start, rq->n_inst, rq->info != nullptr, set != nullptr);
     r->t_submit = clk::now();
     {
         std::lock_guard<std::mutex> lk(sv->m);
@@ -416,6 +448,40 @@ hc_status hc_server_submit(hc_server *sv, const hc_request *rq, int64_t *ticket)
         sv->pending.push_back(r);
     }
     sv->cv_dispatch.notify_one();
+    return HC_OK;
+}
+
+hc_status hc_server_add_start_set(hc_server *sv, const hc_system *sys, const hc_c64 *start, int32_t n_start,
+                                  const hc_c64 *p_start, const hc_start_set **out)
+{
+    clear_error();
+    if (!sv || !sys || !out || !start || n_start < 1) return fail(HC_E_INVALID, "hc_server_add_start_set: bad argument");
+    if (sys->device != sv->ctx->device) return fail(HC_E_INVALID, "hc_server_add_start_set: system on another device");
+    if (sys->kind == HC_PARAMETER && sys->n_params > 0 && !p_start)
+        return fail(HC_E_INVALID, "hc_server_add_start_set: a parameter homotopy needs p_start");
+    hc_start_set *set = new (std::nothrow) hc_start_set;
+    if (!set) return fail(HC_E_OOM, "hc_server_add_start_set: out of host memory");
+    set->sys = sys;
+    set->n_start = n_start;
+    const size_t bs = (size_t)n_start * sys->n * sizeof(hc_c64);
+    const size_t bp = p_start ? (size_t)sys->n_params * sizeof(hc_c64) : 0;
+    hipError_t e = hipSetDevice(sv->ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&set->d_start, bs);
+    if (e == hipSuccess) e = hipMemcpy(set->d_start, start, bs, hipMemcpyHostToDevice);
+    if (e == hipSuccess && bp) e = hipMalloc(&set->d_pstart, bp);
+    if (e == hipSuccess && bp) e = hipMemcpy(set->d_pstart, p_start, bp, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(set->d_start);
+        (void)hipFree(set->d_pstart);
+        delete set;
+        return fail(e == hipErrorOutOfMemory ? HC_E_OOM : HC_E_DEVICE, "hc_server_add_start_set: %s",
+                    hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->m);
+        sv->start_sets.push_back(set);
+    }
+    *out = set;
     return HC_OK;
 }
 
@@ -502,6 +568,11 @@ hc_status hc_server_destroy(hc_server *sv)
         s.in.release();
         s.out.release();
         if (s.ctx) hc_destroy(s.ctx);
+    }
+    for (hc_start_set *set : sv->start_sets) {
+        (void)hipFree(set->d_start);
+        (void)hipFree(set->d_pstart);
+        delete set;
     }
     delete sv;
     return HC_OK;

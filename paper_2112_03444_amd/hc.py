@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
                  "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual",
-                 "crossing_check", "per_instance_start")]
+                 "crossing_check", "per_instance_start", "table_layout")]
 
 
 class Job(ctypes.Structure):
@@ -117,6 +117,10 @@ def lib():
         L.hc_track.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P]
         L.hc_track_device.restype = ctypes.c_int
         L.hc_track_device.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P]
+        L.hc_tune_save.restype = ctypes.c_int
+        L.hc_tune_save.argtypes = [P, ctypes.c_char_p]
+        L.hc_tune_load.restype = ctypes.c_int
+        L.hc_tune_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I32)]
         L.hc_autotune.restype = ctypes.c_int
         L.hc_autotune.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P,
                                   ctypes.POINTER(Opts)]
@@ -354,6 +358,16 @@ class Context:
                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best)))
         return best
 
+    def tune_save(self, path: str):
+        """hc_tune_save: the autotuner's choices to a text file."""
+        _check(lib().hc_tune_save(self.handle, os.fsencode(path)))
+
+    def tune_load(self, path: str) -> int:
+        """hc_tune_load: merge stored autotuner choices; returns the entry count."""
+        n = ctypes.c_int32()
+        _check(lib().hc_tune_load(self.handle, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
     def track_piecewise(self, s: System, waypoints, start, opts: Optional[Opts] = None):
         """Parameter homotopy along a piecewise-linear path of coefficient
         vectors: waypoints[0] [n_params] (shared start instance), then
@@ -458,7 +472,7 @@ class Request(ctypes.Structure):
     _fields_ = [("sys", ctypes.c_void_p), ("n_start", ctypes.c_int32), ("n_inst", ctypes.c_int32),
                 ("start", ctypes.c_void_p), ("p_start", ctypes.c_void_p), ("p_target", ctypes.c_void_p),
                 ("gamma", ctypes.c_void_p), ("endpoints", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("info", ctypes.c_void_p)]
+                ("info", ctypes.c_void_p), ("start_set", ctypes.c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
@@ -485,6 +499,8 @@ def _bind_server():
     L.hc_server_create.argtypes = [P, ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
     L.hc_server_submit.restype = ctypes.c_int
     L.hc_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(I64)]
+    L.hc_server_add_start_set.restype = ctypes.c_int
+    L.hc_server_add_start_set.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(P)]
     L.hc_server_poll.restype = ctypes.c_int
     L.hc_server_poll.argtypes = [P, I64, ctypes.POINTER(ctypes.c_int32)]
     L.hc_server_wait.restype = ctypes.c_int
@@ -496,6 +512,14 @@ def _bind_server():
     L.hc_server_destroy.restype = ctypes.c_int
     L.hc_server_destroy.argtypes = [P]
     _server_bound = True
+
+
+class StartSet:
+    """A start set resident on a server's device (hc_server_add_start_set)."""
+
+    def __init__(self, handle, n_start: int):
+        self.handle = handle
+        self.n_start = n_start
 
 
 class Server:
@@ -517,8 +541,18 @@ class Server:
         self.ctx = ctx
         self._out = {}
 
+    def add_start_set(self, s: System, start, p_start=None) -> "StartSet":
+        """hc_server_add_start_set: start points [n_start, n] (and p_start) kept on
+        the device for requests that name the returned set."""
+        st_pts = np.ascontiguousarray(start, np.complex128).reshape(-1, s.n)
+        ps = None if p_start is None else np.ascontiguousarray(p_start, np.complex128)
+        h = ctypes.c_void_p()
+        _check(lib().hc_server_add_start_set(self.handle, s.handle, _ptr(st_pts), st_pts.shape[0], _ptr(ps),
+                                             ctypes.byref(h)))
+        return StartSet(h, st_pts.shape[0])
+
     def submit(self, s: System, p_target, gamma=None, start=None, p_start=None, n_start=None,
-               with_info: bool = False) -> int:
+               with_info: bool = False, start_set: "Optional[StartSet]" = None) -> int:
         p = np.ascontiguousarray(p_target, np.complex128)
         if p.ndim == 1:
             p = p[None, :]
@@ -527,13 +561,14 @@ class Server:
             np.broadcast_to(np.asarray(gamma, np.complex128), (n_inst,)))
         st_pts = None if start is None else np.ascontiguousarray(start, np.complex128).reshape(-1, s.n)
         if n_start is None:
-            n_start = s.bezout if st_pts is None else st_pts.shape[0]
+            n_start = start_set.n_start if start_set is not None else \
+                s.bezout if st_pts is None else st_pts.shape[0]
         ps = None if p_start is None else np.ascontiguousarray(p_start, np.complex128)
         ep = np.zeros((n_inst, n_start, s.n), np.complex128)
         status = np.zeros((n_inst, n_start), np.int32)
         info = np.zeros((n_inst, n_start), INFO_DTYPE) if with_info else None
         r = Request(s.handle, n_start, n_inst, _ptr(st_pts), _ptr(ps), _ptr(p), _ptr(g), _ptr(ep), _ptr(status),
-                    _ptr(info))
+                    _ptr(info), None if start_set is None else start_set.handle)
         t = ctypes.c_int64()
         _check(lib().hc_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
         self._out[t.value] = (ep, status, info)

@@ -10,6 +10,7 @@ the finite solution sets match the FP64 oracle within 1e-9.
 import numpy as np
 import pytest
 
+import _parity
 import hc_inputs
 import oracle
 
@@ -32,18 +33,9 @@ def ctx(hc):
 
 
 def rel_match(a, b):
-    """Greedy one-to-one nearest matching of the rows of a onto the rows of b;
+    """One-to-one nearest matching of the rows of a (GPU) and b (oracle);
     returns the worst relative distance (inf if the sizes differ)."""
-    if len(a) != len(b):
-        return np.inf
-    b = list(b)
-    worst = 0.0
-    for p in a:
-        d = [np.max(np.abs(p - q)) / max(1.0, np.max(np.abs(q))) for q in b]
-        j = int(np.argmin(d))
-        worst = max(worst, d[j])
-        b.pop(j)
-    return worst
+    return _parity.match_one_to_one(a, b)
 
 
 def finite_set(ep, st, ok):
@@ -309,11 +301,12 @@ def test_batch_of_uneven_jobs_equals_single_calls(hc, ctx, precision):
     dev = torch.device("cuda:0")
     opts = hc.default_opts(precision=precision)
     specs = [(3, 2, None, 11), (5, 3, 20, 12), (8, 4, None, 13), (6, 1, 50, 14), (2, 5, None, 15)]
-    jobs, refs = [], []
+    jobs, refs, oracle_in = [], [], []
     for n, n_inst, n_start, seed in specs:
         S, coef, gam = hc_inputs.dense_quadratic_instances(n, n_inst, seed=seed)
         sysh = ctx.load_system(S)
         ns = n_start if n_start is not None else sysh.bezout
+        oracle_in.append((S, coef, gam, ns))
         p = torch.from_numpy(coef).to(dev)
         g = torch.from_numpy(gam).to(dev)
         ref = [torch.empty((n_inst, ns, n), dtype=torch.complex128, device=dev),
@@ -348,6 +341,18 @@ def test_batch_of_uneven_jobs_equals_single_calls(hc, ctx, precision):
         np.testing.assert_array_equal(j["endpoints"].cpu().numpy(), r[0])
         np.testing.assert_array_equal(j["status"].cpu().numpy(), r[1])
         np.testing.assert_array_equal(j["info"].cpu().numpy(), r[2])
+    # and every job against the oracle, instance by instance (the same start
+    # points: the first n_start total-degree points, or the solved instance's roots)
+    for j, (Sj, cj, gj, ns) in zip(jobs, oracle_in):
+        starts = np.stack([oracle.total_degree_start(Sj, b) for b in range(ns)])
+        oep, ost, _ = oracle.track(Sj, cj, gj, start=starts)
+        ep_j, st_j = j["endpoints"].cpu().numpy(), j["status"].cpu().numpy()
+        for i in range(len(cj)):
+            check_instance_parity(ep_j[i], st_j[i], oep[i], ost[i], hc)
+    oep, ost, _ = oracle.track(S, coef[1:], start=e0[0], coef0=coef[0], kind=oracle.LINEAR)
+    for i in range(2):
+        check_instance_parity(jobs[-1]["endpoints"].cpu().numpy()[i], jobs[-1]["status"].cpu().numpy()[i],
+                              oep[i], ost[i], hc)
 
 
 def test_batch_rejects_unsupported(hc, ctx):

@@ -93,6 +93,38 @@ def test_vision_and_large_requests_in_the_mix(hc, ctx):
     srv.close()
 
 
+def test_resident_start_set_requests_equal_copied_ones(hc, ctx):
+    """Triangulation requests that name a start set kept on the device give,
+    request by request, what the same requests with copied start points give,
+    and the oracle's roots; a set is refused for another system or with start
+    points in the request."""
+    import _parity
+    import oracle
+    import hc_inputs.vision as V
+    opts = hc.default_opts(precision="mixed")
+    S = V.triangulation_system()
+    tri = ctx.load_system(S, kind=hc.HC_PARAMETER)
+    c0, sols = V.start_instance()
+    _, tcoef, _ = V.triangulation_instances(3, seed=6400)
+    srv = hc.Server(ctx, max_inflight=2, max_batch_requests=4, opts=opts)
+    rs = srv.add_start_set(tri, sols, p_start=c0)
+    a = [srv.submit(tri, tcoef[k:k + 1], start_set=rs) for k in range(3)]
+    b = [srv.submit(tri, tcoef[k:k + 1], start=sols, p_start=c0) for k in range(3)]
+    oep, ost, _ = oracle.track(S, tcoef, start=sols, coef0=c0, kind=oracle.LINEAR)
+    for k in range(3):
+        ea, sa, _ = srv.wait(a[k])
+        eb, sb, _ = srv.wait(b[k])
+        np.testing.assert_array_equal(ea, eb)
+        np.testing.assert_array_equal(sa, sb)
+        _parity.check_sets(ea[0], sa[0], oep[k], ost[k], hc.HC_T_SUCCESS)
+    s8 = ctx.load_system(hc_inputs.dense_quadratic_system(8))
+    with pytest.raises(hc.HcError):
+        srv.submit(s8, np.ones((1, 360)), start_set=rs)
+    with pytest.raises(hc.HcError):
+        srv.submit(tri, tcoef[:1], start=sols, start_set=rs)
+    srv.close()
+
+
 def test_tight_budget_still_completes(hc, ctx):
     opts = hc.default_opts(precision="fp64")
     sysh = ctx.load_system(hc_inputs.dense_quadratic_system(7))

@@ -40,10 +40,31 @@ def test_library_exports_every_declared_symbol(hc):
         assert getattr(L, n) is not None
 
 
-def test_struct_layouts_match_header(hc):
-    assert ctypes.sizeof(hc.Opts) == 12 * 8 + 12 * 4
+def test_struct_layouts_match_header(hc, tmp_path):
+    """The binding's ctypes structures have the C compiler's sizes and field
+    offsets for the header's structs."""
+    structs = {"hc_opts": hc.Opts, "hc_system_desc": hc.hc.SystemDesc, "hc_job": hc.hc.Job,
+               "hc_profile": hc.hc.Profile, "hc_request": hc.hc.Request, "hc_server_opts": hc.hc.ServerOpts,
+               "hc_server_stats": hc.hc.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
     assert hc.INFO_DTYPE.itemsize == 32
-    assert ctypes.sizeof(hc.hc.SystemDesc) == 4 * 2 + 8 * 2 + 4 * 2 + 8 * 4
 
 
 def test_default_opts(hc):
