@@ -21,9 +21,9 @@ _LIB = os.path.join(_HERE, "liborc.so")
 TOTAL_DEGREE = 0
 LINEAR = 1
 
-SUCCESS, AT_INFINITY, MIN_STEP, MAX_STEPS, SINGULAR, NONFINITE, REFINE_FAILED = range(7)
+SUCCESS, AT_INFINITY, MIN_STEP, MAX_STEPS, SINGULAR, NONFINITE, REFINE_FAILED, SINGULAR_END = range(8)
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
-                "REFINE_FAILED"]
+                "REFINE_FAILED", "SINGULAR_END"]
 
 
 class Opts(ctypes.Structure):
@@ -63,6 +63,26 @@ def default_opts(**kw) -> Opts:
     d = dict(DEFAULTS)
     d.update(kw)
     return Opts(**d)
+
+
+class EgOpts(ctypes.Structure):
+    """Power-series end-game options (orc_eg_opts in hc_oracle.c)."""
+    _fields_ = [("s0", ctypes.c_double), ("beta", ctypes.c_double), ("tol", ctypes.c_double),
+                ("tol_inf", ctypes.c_double),
+                ("tau", ctypes.c_double), ("h_min", ctypes.c_double), ("max_newton", ctypes.c_int),
+                ("max_samples", ctypes.c_int),
+                ("max_cycle", ctypes.c_int), ("every", ctypes.c_int)]
+
+
+# The end-game's constants (ours: the paper has no end-game).
+EG_DEFAULTS = dict(s0=0.1, beta=0.25, tol=1e-9, tol_inf=1e-3, tau=1e-10, h_min=1e-14, max_newton=5, max_samples=16,
+                   max_cycle=8, every=0)
+
+
+def default_eg_opts(**kw) -> EgOpts:
+    d = dict(EG_DEFAULTS)
+    d.update(kw)
+    return EgOpts(**d)
 
 
 class _System(ctypes.Structure):
@@ -126,6 +146,13 @@ def _load():
         lib.orc_track_batch.argtypes = [ctypes.POINTER(_System), ctypes.c_int, P, P, P, P,
                                         ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts),
                                         ctypes.c_int, P, P, P]
+        lib.orc_track_batch_eg.restype = ctypes.c_int
+        lib.orc_track_batch_eg.argtypes = [ctypes.POINTER(_System), ctypes.c_int, P, P, P, P,
+                                           ctypes.c_int, ctypes.c_int, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(EgOpts), ctypes.c_int, P, P, P, P]
+        lib.orc_eg_extrapolate.restype = ctypes.c_int
+        lib.orc_eg_extrapolate.argtypes = [ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int), P]
         lib.orc_eval_system.restype = None
         lib.orc_eval_system.argtypes = [ctypes.POINTER(_System), P, P, P, P]
         lib.orc_homotopy_eval_flat.restype = None
@@ -248,6 +275,18 @@ def newton_trace(system, x0, t, iters, coef1, gamma=1.0, coef0=None, kind=TOTAL_
     return norms, out
 
 
+def eg_extrapolate(y0, y1, y2, beta, max_cycle=8):
+    """The end-game's estimator: (cycle number, extrapolated vector) from samples
+    at s, beta s, beta^2 s, or None if they do not decay."""
+    a, b, c = _c128(y0), _c128(y1), _c128(y2)
+    E = np.zeros_like(a)
+    cyc = ctypes.c_int(0)
+    if _load().orc_eg_extrapolate(len(a), _ptr(a), _ptr(b), _ptr(c), float(beta), int(max_cycle),
+                                  ctypes.byref(cyc), _ptr(E)):
+        return None
+    return cyc.value, E
+
+
 def residual(system, coef, x) -> float:
     s = _Sys(system)
     c, xx = _c128(coef), _c128(x)
@@ -255,14 +294,16 @@ def residual(system, coef, x) -> float:
 
 
 def track(system, coef1, gamma=None, start=None, coef0=None, kind=TOTAL_DEGREE, opts=None,
-          n_threads: Optional[int] = None):
+          n_threads: Optional[int] = None, endgame=None):
     """Track every start point for every instance.
 
     coef1: [n_inst, n_terms] target coefficients; gamma: [n_inst] (total degree);
     start: [n_start, n] start points or None for the total-degree start points;
-    coef0: [n_terms] start coefficients (LINEAR).
+    coef0: [n_terms] start coefficients (LINEAR); endgame: None, True (the
+    default end-game options) or an EgOpts.
     Returns endpoints [n_inst, n_start, n], status [n_inst, n_start] (int32),
-    info [n_inst, n_start] (INFO_DTYPE).
+    info [n_inst, n_start] (INFO_DTYPE); with an end-game also the cycle numbers
+    [n_inst, n_start] (int32, 0 where no end-game converged).
     """
     s = _Sys(system)
     c1 = _c128(coef1)
@@ -284,9 +325,18 @@ def track(system, coef1, gamma=None, start=None, coef0=None, kind=TOTAL_DEGREE, 
     info = np.zeros((n_inst, n_start), INFO_DTYPE)
     o = opts if opts is not None else default_opts()
     nt = n_threads if n_threads is not None else default_threads()
-    rc = _load().orc_track_batch(ctypes.byref(s.c), kind, _ptr(c0), _ptr(c1), _ptr(g), _ptr(st),
-                                 n_start, n_inst, ctypes.byref(o), int(nt), _ptr(ep),
-                                 _ptr(status), _ptr(info))
+    if endgame is None or endgame is False:
+        rc = _load().orc_track_batch(ctypes.byref(s.c), kind, _ptr(c0), _ptr(c1), _ptr(g), _ptr(st),
+                                     n_start, n_inst, ctypes.byref(o), int(nt), _ptr(ep),
+                                     _ptr(status), _ptr(info))
+        if rc != 0:
+            raise ValueError("orc_track_batch rejected its arguments")
+        return ep, status, info
+    eg = default_eg_opts() if endgame is True else endgame
+    cyc = np.zeros((n_inst, n_start), np.int32)
+    rc = _load().orc_track_batch_eg(ctypes.byref(s.c), kind, _ptr(c0), _ptr(c1), _ptr(g), _ptr(st),
+                                    n_start, n_inst, ctypes.byref(o), ctypes.byref(eg), int(nt), _ptr(ep),
+                                    _ptr(status), _ptr(info), _ptr(cyc))
     if rc != 0:
-        raise ValueError("orc_track_batch rejected its arguments")
-    return ep, status, info
+        raise ValueError("orc_track_batch_eg rejected its arguments")
+    return ep, status, info, cyc

@@ -80,7 +80,8 @@ typedef struct {
 
 enum {
     ORC_SUCCESS = 0, ORC_AT_INFINITY = 1, ORC_MIN_STEP = 2, ORC_MAX_STEPS = 3,
-    ORC_SINGULAR = 4, ORC_NONFINITE = 5, ORC_REFINE_FAILED = 6
+    ORC_SINGULAR = 4, ORC_NONFINITE = 5, ORC_REFINE_FAILED = 6,
+    ORC_SINGULAR_END = 7   /* the end-game's estimate of a singular endpoint        */
 };
 
 /* ---- small helpers -------------------------------------------------------- */
@@ -322,37 +323,38 @@ static int refine_endpoint(const orc_homotopy *Hm, const orc_opts *o, cplx *x, o
 
 /* ---- one path ------------------------------------------------------------------- */
 
-/* Track x(t) from x0 at t = 0 to t = 1 (section 3): per step an RK4 prediction to
- * t + h, then at most max_newton Newton corrections at t + h; accept when the
- * correction is small, else halve h.  Then refine at t = 1.  Returns the status. */
-int orc_track_one(const orc_homotopy *Hm, const orc_opts *o, const cplx *x0, cplx *x_out, orc_info *info)
+/* The step loop of section 3 from (x, *t) up to t_final: per step an RK4 prediction
+ * to t + h, then at most max_newton Newton corrections at t + h; accept when the
+ * correction is below tau (1 + ||x||_2), else halve h.  The last step is clipped
+ * to land exactly on t_final.  x, *t, *h, *succ and info carry the path's state
+ * from one call to the next.  Returns -1 once t_final is reached, else the
+ * failure status. */
+static int track_segment(const orc_homotopy *Hm, const orc_opts *o, double tau, int max_newton, double h_min,
+                         cplx *x, double *t_io, double *h_io, int *succ_io, double t_final,
+                         orc_info *info)
 {
     int n = Hm->S->n;
-    cplx x[ORC_MAXN], xs[ORC_MAXN], d[ORC_MAXN];
-    double t = 0.0, h = o->h0;
-    int succ = 0, status = -1;
-    memset(info, 0, sizeof(*info));
-    info->residual = NAN;
-    for (int j = 0; j < n; j++) x[j] = x0[j];
-    if (!all_finite(n, x)) status = ORC_NONFINITE;
+    cplx xs[ORC_MAXN], d[ORC_MAXN];
+    double t = *t_io, h = *h_io;
+    int succ = *succ_io, status = -1;
 
-    while (status < 0 && t < 1.0) {
+    while (t < t_final) {
         if (info->steps + info->rejects >= o->max_steps) { status = ORC_MAX_STEPS; break; }
         double hu, tn;
-        if (h >= 1.0 - t) { hu = 1.0 - t; tn = 1.0; }   /* land exactly on t = 1 */
-        else              { hu = h;       tn = t + h; }
+        if (h >= t_final - t) { hu = t_final - t; tn = t_final; }   /* land exactly on t_final */
+        else                  { hu = h;           tn = t + h; }
 
         int converged = 0;
         int bad = rk4_step(Hm, x, t, hu, tn, xs);
         if (bad == 2) { status = ORC_NONFINITE; break; }
         if (!bad) {
-            for (int it = 0; it < o->max_newton; it++) {
+            for (int it = 0; it < max_newton; it++) {
                 if (newton_delta(Hm, xs, tn, d)) break;
                 info->newton_its++;
                 for (int j = 0; j < n; j++) xs[j] += d[j];
                 double nd = norm2(n, d), nx = norm2(n, xs);
                 if (it == 0 && !(nd <= o->pred_tol * (1.0 + nx))) break;
-                if (nd <= o->tau * (1.0 + nx)) { converged = 1; break; }
+                if (nd <= tau * (1.0 + nx)) { converged = 1; break; }
             }
         }
         if (converged) {
@@ -365,12 +367,217 @@ int orc_track_one(const orc_homotopy *Hm, const orc_opts *o, const cplx *x0, cpl
             info->rejects++;
             succ = 0;
             h *= o->beta_dec;
-            if (h < o->h_min) { status = ORC_MIN_STEP; break; }
+            if (h < h_min) { status = ORC_MIN_STEP; break; }
         }
     }
+    *t_io = t;
+    *h_io = h;
+    *succ_io = succ;
+    return status;
+}
+
+/* Track x(t) from x0 at t = 0 to t = 1 (section 3), then refine at t = 1.
+ * Returns the status; *t_end = the t the path stopped at. */
+static int track_one_t(const orc_homotopy *Hm, const orc_opts *o, const cplx *x0, cplx *x_out,
+                       orc_info *info, double *t_end)
+{
+    int n = Hm->S->n;
+    cplx x[ORC_MAXN];
+    double t = 0.0, h = o->h0;
+    int succ = 0, status = -1;
+    memset(info, 0, sizeof(*info));
+    info->residual = NAN;
+    for (int j = 0; j < n; j++) x[j] = x0[j];
+    if (!all_finite(n, x)) status = ORC_NONFINITE;
+    if (status < 0) status = track_segment(Hm, o, o->tau, o->max_newton, o->h_min, x, &t, &h, &succ, 1.0, info);
     if (status < 0) status = refine_endpoint(Hm, o, x, info);
     for (int j = 0; j < n; j++) x_out[j] = x[j];
+    *t_end = t;
     return status;
+}
+
+int orc_track_one(const orc_homotopy *Hm, const orc_opts *o, const cplx *x0, cplx *x_out, orc_info *info)
+{
+    double t;
+    return track_one_t(Hm, o, x0, x_out, info, &t);
+}
+
+/* ---- power-series end-game ------------------------------------------------------ */
+
+/* The paper does not treat singular endpoints (section 2 only warns that the number
+ * of solutions HC reports needs checking).  This follows the published power-series
+ * end-game of Morgan, Sommese and Wampler ("A power series method for computing
+ * singular solutions to nonlinear analytic systems", Numer. Math. 63, 1992):
+ * near t = 1, with s = 1 - t, a path has a convergent fractional power series
+ * x(s) = sum_j a_j s^(j/c) whose cycle number c >= 1 makes x analytic in
+ * sigma = s^(1/c) (meromorphic, for a path that goes to infinity).  The series is
+ * taken of the point in projective coordinates on a fixed patch,
+ * y(s) = (1, x(s)) / (a . (1, x(s))), which stays bounded at infinity (y_0 -> 0)
+ * as well as at finite endpoints.  The path is sampled at the geometric points
+ * s_k = s0 beta^k, c is estimated from the decay of successive sample differences
+ * (|y_k - y_(k+1)| ~ s_k^(1/c)), and y(0) is extrapolated from the last three
+ * samples by the quadratic through them in sigma; x = y_(1..n) / y_0.  Readings
+ * (the constants are ours): samples from k = 1 on, tracked with a tighter
+ * corrector (eg->tau, eg->max_newton) and a smaller minimum step (eg->h_min: the
+ * steps shrink with s there) inside the zone [1 - s0, 1]; the end-game has
+ * converged when two successive estimates of y agree to eg->tol |y|_inf, or to
+ * eg->tol_inf |y|_inf with an estimated y_0 below |y|_inf / inf_bound (the affine
+ * tracker's bound on |x|: a path to infinity, whose y_0 -> 0 needs no more digits
+ * to be told from a finite endpoint); the
+ * patch is a_j = exp(2 pi i frac((j + 1) phi)), phi = (sqrt 5 - 1) / 2 (the
+ * golden-ratio Weyl sequence, j = 0..n), fixed so that both sides of a
+ * comparison use the same one. */
+typedef struct {
+    double s0;        /* zone [1 - s0, 1]                                          */
+    double beta;      /* sample ratio s_(k+1) = beta s_k                            */
+    double tol;       /* successive estimates this close (relative): converged     */
+    double tol_inf;   /* ... this close, with y_0 below |y|_inf / inf_bound: at infinity */
+    double tau;       /* corrector tolerance inside the zone                       */
+    double h_min;     /* smallest step inside the zone                              */
+    int max_newton;   /* corrector iterations per step inside the zone             */
+    int max_samples;  /* samples s_1 .. s_max_samples                              */
+    int max_cycle;    /* largest cycle number considered                           */
+    int every;        /* 1: every path that reaches the zone takes the end-game    */
+} orc_eg_opts;
+
+/* Cycle number and extrapolated x(0) from three samples y0, y1, y2 taken at s,
+ * beta s, beta^2 s.  Returns 0 and sets *c, E; 1 if the samples do not decay. */
+static int eg_estimate(int n, const cplx *y0, const cplx *y1, const cplx *y2, double beta, int max_cycle,
+                       int *c, cplx *E)
+{
+    cplx d[ORC_MAXN + 1];
+    for (int j = 0; j < n; j++) d[j] = y0[j] - y1[j];
+    double d1 = norminf(n, d);
+    for (int j = 0; j < n; j++) d[j] = y1[j] - y2[j];
+    double d2 = norminf(n, d);
+    if (d2 == 0.0) {              /* the path has stopped moving: x(0) = y2 */
+        *c = 1;
+        for (int j = 0; j < n; j++) E[j] = y2[j];
+        return 0;
+    }
+    if (!(d2 < d1)) return 1;     /* not decaying (yet), or heading to infinity */
+    /* d2 / d1 ~ beta^(1/c) */
+    double cr = log(beta) / log(d2 / d1);
+    int ci = (int)floor(cr + 0.5);
+    if (ci < 1) ci = 1;
+    if (ci > max_cycle) ci = max_cycle;
+    *c = ci;
+    /* the samples sit at sigma0, q sigma0, q^2 sigma0 with q = beta^(1/c); the
+     * lines through consecutive pairs meet sigma = 0 at R_a, R_b, and the quadratic
+     * through all three at (R_b - q^2 R_a) / (1 - q^2) */
+    double q = pow(beta, 1.0 / ci);
+    for (int j = 0; j < n; j++) {
+        cplx ra = (y1[j] - q * y0[j]) / (1.0 - q);
+        cplx rb = (y2[j] - q * y1[j]) / (1.0 - q);
+        E[j] = (rb - q * q * ra) / (1.0 - q * q);
+    }
+    return 0;
+}
+
+/* y = (1, x) / (a . (1, x)) on the end-game's patch (n + 1 entries). */
+static void eg_project(int n, const cplx *x, cplx *y)
+{
+    const double phi = 0.5 * (sqrt(5.0) - 1.0);
+    cplx den = 0.0;
+    for (int j = 0; j <= n; j++) {
+        double f = (j + 1) * phi;
+        f -= floor(f);
+        den += cexp(I * (2.0 * 3.14159265358979323846 * f)) * (j == 0 ? 1.0 : x[j - 1]);
+    }
+    y[0] = 1.0 / den;
+    for (int j = 0; j < n; j++) y[j + 1] = x[j] / den;
+}
+
+/* End-game of one path from its start point x0: tracked like orc_track_one up to
+ * t = 1 - s0, then sampled at s_1, s_2, ... as above.  Returns -1 and sets x_out
+ * (= y_(1..n) / y_0 of the estimate, infinite entries for y_0 = 0), *cycle when
+ * two successive estimates agree; else the status at which the path stopped (a
+ * tracking failure, or ORC_MIN_STEP when max_samples were not enough), with x_out
+ * the last point tracked.  info counts this run's steps. */
+static int endgame_one(const orc_homotopy *Hm, const orc_opts *o, const orc_eg_opts *eg, const cplx *x0,
+                       cplx *x_out, orc_info *info, int *cycle)
+{
+    int n = Hm->S->n, m = Hm->S->n + 1;
+    cplx x[ORC_MAXN], y[3][ORC_MAXN + 1], E[ORC_MAXN + 1], Ep[ORC_MAXN + 1];
+    double t = 0.0, h = o->h0, s = eg->s0;
+    int succ = 0, have_prev = 0, status;
+    memset(info, 0, sizeof(*info));
+    info->residual = NAN;
+    for (int j = 0; j < n; j++) x[j] = x0[j];
+    if (!all_finite(n, x)) return ORC_NONFINITE;
+    status = track_segment(Hm, o, o->tau, o->max_newton, o->h_min, x, &t, &h, &succ, 1.0 - s, info);
+    for (int k = 1; status < 0 && k <= eg->max_samples; k++) {
+        s *= eg->beta;
+        status = track_segment(Hm, o, eg->tau, eg->max_newton, eg->h_min, x, &t, &h, &succ, 1.0 - s, info);
+        if (status >= 0) break;
+        memmove(y[0], y[1], sizeof(y[0]) * 2);
+        eg_project(n, x, y[2]);
+        if (k < 3) continue;
+        int c;
+        if (eg_estimate(m, y[0], y[1], y[2], eg->beta, eg->max_cycle, &c, E)) {
+            have_prev = 0;
+            continue;
+        }
+        if (have_prev) {
+            cplx diff[ORC_MAXN + 1];
+            for (int j = 0; j < m; j++) diff[j] = E[j] - Ep[j];
+            double dn = norminf(m, diff), en = norminf(m, E);
+            /* settled on a finite point, or on y_0 = 0 as closely as the affine
+             * bound |x| <= inf_bound can tell (a path to infinity) */
+            if (dn <= eg->tol * en || (dn <= eg->tol_inf * en && cabs(E[0]) * o->inf_bound <= en)) {
+                for (int j = 0; j < n; j++) x_out[j] = E[j + 1] / E[0];
+                *cycle = c;
+                return -1;
+            }
+        }
+        for (int j = 0; j < m; j++) Ep[j] = E[j];
+        have_prev = 1;
+    }
+    for (int j = 0; j < n; j++) x_out[j] = x[j];
+    return status < 0 ? ORC_MIN_STEP : status;
+}
+
+/* A path that stopped with `status` at t_end gets the end-game when it failed in
+ * the zone [1 - s0, 1] or reached t = 1 without a regular endpoint; with
+ * eg->every, every path that reached the zone and met no non-finite value. */
+static int eg_candidate(const orc_eg_opts *eg, int status, double t_end)
+{
+    if (eg->every) return status != ORC_NONFINITE && t_end >= 1.0 - eg->s0;
+    if (status == ORC_REFINE_FAILED || status == ORC_SINGULAR) return 1;
+    return (status == ORC_MIN_STEP || status == ORC_MAX_STEPS) && t_end >= 1.0 - eg->s0;
+}
+
+/* orc_track_one, and for an end-game candidate the end-game from the start point.
+ * If the end-game converges, its estimate E is classified: above inf_bound (y_0 ->
+ * 0) ORC_AT_INFINITY; cycle number 1 (the path ends at a point where it is
+ * analytic in s) the usual refinement and classification at t = 1 from E; cycle
+ * number >= 2 (a singular endpoint: Newton would only converge linearly) the
+ * endpoint is E itself, status ORC_SINGULAR_END, with its residual.  If it does
+ * not converge the first result stands.  info counts the steps of both runs;
+ * *cycle = the cycle number (0 without a converged end-game). */
+static int track_one_eg(const orc_homotopy *Hm, const orc_opts *o, const orc_eg_opts *eg, const cplx *x0,
+                        cplx *x_out, orc_info *info, int *cycle)
+{
+    int n = Hm->S->n;
+    double t_end;
+    *cycle = 0;
+    int st = track_one_t(Hm, o, x0, x_out, info, &t_end);
+    if (!eg || !eg_candidate(eg, st, t_end)) return st;
+    cplx E[ORC_MAXN];
+    orc_info ie;
+    int c = 0;
+    if (endgame_one(Hm, o, eg, x0, E, &ie, &c) >= 0) return st;
+    info->steps += ie.steps;
+    info->rejects += ie.rejects;
+    info->newton_its += ie.newton_its;
+    info->refine_its = 0;
+    info->residual = NAN;
+    *cycle = c;
+    for (int j = 0; j < n; j++) x_out[j] = E[j];
+    if (!(norminf(n, E) <= o->inf_bound)) return ORC_AT_INFINITY;
+    if (c == 1) return refine_endpoint(Hm, o, x_out, info);
+    info->residual = orc_residual(Hm->S, Hm->c1, E);
+    return ORC_SINGULAR_END;
 }
 
 /* Start point of track b of the total-degree start system G_i = x_i^d_i - 1:
@@ -395,9 +602,11 @@ typedef struct {
     const cplx *c0, *c1, *gamma, *start;
     int n_start, n_inst;
     const orc_opts *o;
+    const orc_eg_opts *eg; /* NULL: no end-game */
     cplx *endpoints;
     int *status;
     orc_info *info;
+    int *cycle;          /* [n_inst][n_start] or NULL */
     long long next;      /* shared work counter */
     pthread_mutex_t lock;
 } batch_job;
@@ -425,9 +634,11 @@ static void *batch_worker(void *arg)
         if (B->start) memcpy(x0, B->start + (size_t)trk * n, sizeof(cplx) * n);
         else orc_total_degree_start(n, Hm.deg, trk, x0);
         orc_info inf;
-        int st = orc_track_one(&Hm, B->o, x0, B->endpoints + (size_t)w * n, &inf);
+        int cyc = 0;
+        int st = track_one_eg(&Hm, B->o, B->eg, x0, B->endpoints + (size_t)w * n, &inf, &cyc);
         B->status[w] = st;
         if (B->info) B->info[w] = inf;
+        if (B->cycle) B->cycle[w] = cyc;
     }
     return NULL;
 }
@@ -437,19 +648,21 @@ static void *batch_worker(void *arg)
  *   c0:    [n_terms] start coefficients (LINEAR only)
  *   gamma: [n_inst] (TOTAL_DEGREE only; NULL = 1)
  *   start: [n_start][n] start points, or NULL for the total-degree start points
- * Outputs endpoints [n_inst][n_start][n], status and (optional) info
+ *   eg:    end-game options, or NULL for none (then every path is orc_track_one's)
+ * Outputs endpoints [n_inst][n_start][n], status and (optional) info and cycle
  * [n_inst][n_start].  Uses n_threads POSIX threads.  Returns 0, or -1 on bad input. */
-int orc_track_batch(const orc_system *S, int kind, const cplx *c0, const cplx *c1,
-                    const cplx *gamma, const cplx *start, int n_start, int n_inst,
-                    const orc_opts *o, int n_threads,
-                    cplx *endpoints, int *status, orc_info *info)
+int orc_track_batch_eg(const orc_system *S, int kind, const cplx *c0, const cplx *c1,
+                       const cplx *gamma, const cplx *start, int n_start, int n_inst,
+                       const orc_opts *o, const orc_eg_opts *eg, int n_threads,
+                       cplx *endpoints, int *status, orc_info *info, int *cycle)
 {
     if (!S || S->n < 1 || S->n > ORC_MAXN || n_start < 0 || n_inst < 0) return -1;
     if (kind == ORC_LINEAR && !c0) return -1;
     if (kind == ORC_LINEAR && !start) return -1;
+    if (eg && (eg->max_samples < 0 || !(eg->beta > 0.0 && eg->beta < 1.0) || eg->max_cycle < 1)) return -1;
     batch_job B;
     B.S = S; B.kind = kind; B.c0 = c0; B.c1 = c1; B.gamma = gamma; B.start = start;
-    B.n_start = n_start; B.n_inst = n_inst; B.o = o;
+    B.n_start = n_start; B.n_inst = n_inst; B.o = o; B.eg = eg; B.cycle = cycle;
     B.endpoints = endpoints; B.status = status; B.info = info;
     B.next = 0;
     pthread_mutex_init(&B.lock, NULL);
@@ -460,6 +673,16 @@ int orc_track_batch(const orc_system *S, int kind, const cplx *c0, const cplx *c
     for (int i = 0; i < n_threads; i++) pthread_join(th[i], NULL);
     pthread_mutex_destroy(&B.lock);
     return 0;
+}
+
+/* orc_track_batch_eg without the end-game. */
+int orc_track_batch(const orc_system *S, int kind, const cplx *c0, const cplx *c1,
+                    const cplx *gamma, const cplx *start, int n_start, int n_inst,
+                    const orc_opts *o, int n_threads,
+                    cplx *endpoints, int *status, orc_info *info)
+{
+    return orc_track_batch_eg(S, kind, c0, c1, gamma, start, n_start, n_inst, o, NULL, n_threads,
+                              endpoints, status, info, NULL);
 }
 
 /* ---- pieces exposed for the pins ------------------------------------------------------ */
@@ -500,6 +723,16 @@ int orc_rk4_fixed(const orc_system *S, int kind, const cplx *c0, const cplx *c1,
     }
     for (int j = 0; j < n; j++) x_out[j] = x[j];
     return 0;
+}
+
+/* The end-game's estimator on its own: cycle number and extrapolated value from
+ * three samples of an m-vector at s, beta s, beta^2 s.  Returns 1 if the samples
+ * do not decay. */
+int orc_eg_extrapolate(int m, const cplx *y0, const cplx *y1, const cplx *y2, double beta, int max_cycle,
+                       int *c, cplx *E)
+{
+    if (m < 1 || m > ORC_MAXN + 1) return 1;
+    return eg_estimate(m, y0, y1, y2, beta, max_cycle, c, E);
 }
 
 /* Plain Newton on H(., t) from x0 for `iters` iterations; norms[k] = ||dx_k||_2. */
