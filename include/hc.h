@@ -34,6 +34,8 @@ extern "C" {
 #endif
 
 #define HC_MAX_N 20 /* largest number of unknowns the GPU path handles */
+/* Size of the fixed device workspace of hc_track_device_noalloc (per device). */
+#define HC_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 typedef struct {
     double re, im;
@@ -251,6 +253,36 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
                           const hc_c64 *gamma, const hc_opts *opts,
                           hc_c64 *endpoints, int32_t *status, hc_track_info *info,
                           void *stream);
+
+/* hc_track_device for callers that cannot allocate device memory: code under
+ * hipGraph stream capture, tight serving loops, hosts that forbid hipMalloc.
+ * Same arguments, results and stream semantics as hc_track_device, but the path
+ * state, the per-instance coefficient tables and the launch counters live in a
+ * fixed device array of HC_NOALLOC_SCRATCH_BYTES per device, held by the
+ * library from load until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocation.  Workspace of one call, in bytes (each part
+ * rounded up to 256): 256 + n_inst n_start (16 n + 40) [+ 16 n_inst n_start in
+ * mixed precision with n_start > 8192] + (n_inst + P) n T (16, + 8 in mixed
+ * precision), where T is the system's table slots per equation and P is 0 for
+ * total degree, 1 for HC_PARAMETER (n_inst with per_instance_start); the
+ * dense n = 8 batch of 512 x 256 paths takes about 27 MB.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (two streams, two contexts, two
+ * threads) race and corrupt each other's paths -- serialise them.  Kernels clear
+ * what must start at zero themselves, so back-to-back calls on one stream are
+ * safe.  Differences from hc_track_device: opts->use_graph is ignored (capture
+ * the call instead), profiling is not recorded, and a table_layout other than
+ * the system's own is served only if hc_autotune or an earlier call already
+ * made that copy.
+ * Errors: as hc_track_device; HC_E_UNSUPPORTED when the workspace exceeds
+ * HC_NOALLOC_SCRATCH_BYTES (the message gives both sizes) or the table layout
+ * would need a new copy. */
+hc_status hc_track_device_noalloc(hc_ctx *ctx, const hc_system *sys,
+                                  const hc_c64 *start, int32_t n_start,
+                                  const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                                  const hc_c64 *gamma, const hc_opts *opts,
+                                  hc_c64 *endpoints, int32_t *status, hc_track_info *info,
+                                  void *stream);
 
 /* Batched complex linear solves A_k x_k = b_k, k < batch (section 6, "Linear
  * System Solver": one fused kernel factors the augmented matrix [A_k | b_k] by

@@ -109,6 +109,9 @@ hc_status hc_create(int device, hc_ctx **out)
         c->arch = c->arch.substr(0, c->arch.find(':'));  // gfx950, without feature flags
         e = hipStreamCreate(&c->own_stream);
     }
+    // the no-allocation entry point's workspace: its address on this device,
+    // looked up once per device
+    if (e == hipSuccess) e = scratch_init(device);
     if (e != hipSuccess) {
         delete c;
         return fail(HC_E_DEVICE, "hc_create: %s", hipGetErrorString(e));
@@ -544,7 +547,8 @@ static std::string tune_key(const hc_ctx *c, const hc_system *s, int precision, 
 // decomposition to the library (tracks_per_item = lanes_per_path = 0; a
 // steps_per_launch of -1 takes the tuned value too, else 0).  May switch the
 // system to its copy in the tuned table layout.
-static hc_status apply_tuning(hc_ctx *c, const hc_system *&s, hc_opts &o, int n_start, int n_inst)
+static hc_status apply_tuning(hc_ctx *c, const hc_system *&s, hc_opts &o, int n_start, int n_inst,
+                              bool may_alloc = true)
 {
     if (o.lanes_per_path == 0 && o.tracks_per_item == 0 && o.table_layout == HC_LAYOUT_AUTO) {
         auto it = c->tune.find(tune_key(c, s, o.precision, n_start, n_inst));
@@ -558,6 +562,9 @@ static hc_status apply_tuning(hc_ctx *c, const hc_system *&s, hc_opts &o, int n_
     }
     if (o.steps_per_launch < 0) o.steps_per_launch = 0;
     if (o.table_layout != HC_LAYOUT_AUTO && o.table_layout != s->layout) {
+        if (!may_alloc && !s->alt)
+            return fail(HC_E_UNSUPPORTED, "table_layout = %d needs a copy of the system in that layout, "
+                        "which the no-allocation entry point does not make", o.table_layout);
         const hc_system *t = alt_layout(c, s);
         if (!t || t->layout != o.table_layout)
             return fail(HC_E_UNSUPPORTED, "opts.table_layout = %d cannot hold this system (n = %d, degree %d)",
@@ -579,7 +586,8 @@ static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                                    const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
                                    const hc_c64 *gamma, const hc_opts *opts_in, hc_c64 *endpoints,
-                                   int32_t *status, hc_track_info *info, hipStream_t st)
+                                   int32_t *status, hc_track_info *info, hipStream_t st,
+                                   bool noalloc = false)
 {
     if (!c || !s) return fail(HC_E_INVALID, "hc_track: NULL context or system");
     if (n_start < 0 || n_inst < 0) return fail(HC_E_INVALID, "hc_track: negative size");
@@ -588,7 +596,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     else hc_default_opts(&o);
     hc_status rc = check_opts(o);
     if (rc != HC_OK) return rc;
-    rc = apply_tuning(c, s, o, n_start, n_inst);
+    rc = apply_tuning(c, s, o, n_start, n_inst, !noalloc);
     if (rc != HC_OK) return rc;
     const bool param = s->kind == HC_PARAMETER;
     if (!param && !start && n_start > s->bezout)
@@ -618,14 +626,28 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const int n_tab = n_inst + (param ? (pis ? n_inst : 1) : 0);
     const size_t coef64 = (size_t)n_tab * n_slots * 2 * sizeof(double);
     const size_t coef32 = mixed ? (size_t)n_tab * n_slots * 2 * sizeof(float) : 0;
-    HIP_TRY(c->state.ensure(state_bytes));
-    HIP_TRY(c->coef.ensure(coef64 + coef32));
-    HIP_TRY(c->counter.ensure(64));
-    char *state_p = static_cast<char *>(c->state.p);
-    char *coef_p = static_cast<char *>(c->coef.p);
-    char *counter_p = static_cast<char *>(c->counter.p);
+    char *state_p, *coef_p, *counter_p;
+    if (noalloc) {
+        // the device's fixed scratch array: counters | state | tables
+        const size_t need = 256 + al256(state_bytes) + al256(coef64 + coef32);
+        if (need > kScratchBytes)
+            return fail(HC_E_UNSUPPORTED, "hc_track_device_noalloc: the call needs %zu workspace bytes, the "
+                        "fixed workspace holds %zu", need, kScratchBytes);
+        char *base = static_cast<char *>(scratch_ptr(c->device));
+        if (!base) return fail(HC_E_DEVICE, "hc_track_device_noalloc: no workspace address for device %d", c->device);
+        counter_p = base;
+        state_p = base + 256;
+        coef_p = state_p + al256(state_bytes);
+    } else {
+        HIP_TRY(c->state.ensure(state_bytes));
+        HIP_TRY(c->coef.ensure(coef64 + coef32));
+        HIP_TRY(c->counter.ensure(64));
+        state_p = static_cast<char *>(c->state.p);
+        coef_p = static_cast<char *>(c->coef.p);
+        counter_p = static_cast<char *>(c->counter.p);
+    }
     unsigned long long *stage_ctr = reinterpret_cast<unsigned long long *>(counter_p + 16);
-    const bool prof = c->profiling;
+    const bool prof = c->profiling && !noalloc;
     if (prof) {
         for (hipEvent_t &e : c->ev)
             if (!e) HIP_TRY(hipEventCreate(&e));
@@ -926,6 +948,16 @@ hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, in
     c->graph_key = key();
     c->graph_valid = true;
     return HC_OK;
+}
+
+hc_status hc_track_device_noalloc(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
+                                  const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
+                                  const hc_c64 *gamma, const hc_opts *opts, hc_c64 *endpoints, int32_t *status,
+                                  hc_track_info *info, void *stream)
+{
+    clear_error();
+    return track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, opts, endpoints, status, info,
+                             static_cast<hipStream_t>(stream), true);
 }
 
 hc_status hc_autotune(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start, const hc_c64 *p_start,

@@ -191,6 +191,13 @@ int queue_waves_terms(int tk, bool fp32, bool param);
 hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st);
 hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long long max_total, hipStream_t st);
 
+// Fixed device workspace of hc_track_device_noalloc (hc_scratch.hip): one
+// kScratchBytes array per device, its address looked up once per device by
+// scratch_init (hc_create); scratch_ptr returns it (null before scratch_init).
+constexpr size_t kScratchBytes = (size_t)HC_NOALLOC_SCRATCH_BYTES;
+hipError_t scratch_init(int device);
+void *scratch_ptr(int device);
+
 // Measured vector FMA rate (hc_peak.hip), TFLOP/s.
 hipError_t measure_peak_fma(bool fp64, double *tflops, hipStream_t st);
 

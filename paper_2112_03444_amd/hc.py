@@ -27,6 +27,7 @@ HC_FP64, HC_MIXED = 0, 1
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
                 "REFINE_FAILED"]
 HC_MAX_N = 20
+HC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed workspace of hc_track_device_noalloc, per device
 HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
 
 
@@ -117,6 +118,8 @@ def lib():
         L.hc_track.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P]
         L.hc_track_device.restype = ctypes.c_int
         L.hc_track_device.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P]
+        L.hc_track_device_noalloc.restype = ctypes.c_int
+        L.hc_track_device_noalloc.argtypes = [P, P, P, I32, P, P, I32, P, ctypes.POINTER(Opts), P, P, P, P]
         L.hc_tune_save.restype = ctypes.c_int
         L.hc_tune_save.argtypes = [P, ctypes.c_char_p]
         L.hc_tune_load.restype = ctypes.c_int
@@ -312,10 +315,13 @@ class Context:
         return ep, status, info
 
     def track_device(self, s: System, p_target, gamma, endpoints, status, info=None, start=None,
-                     p_start=None, n_start: Optional[int] = None, opts: Optional[Opts] = None, stream=None):
+                     p_start=None, n_start: Optional[int] = None, opts: Optional[Opts] = None, stream=None,
+                     noalloc: bool = False):
         """Device-pointer hc_track_device on torch tensors (complex128 for complex
         arrays, int32 status, info as a [.., 32]-byte uint8 tensor or None).
-        `stream` is a torch.cuda.Stream (default: the current stream)."""
+        `stream` is a torch.cuda.Stream (default: the current stream).  With
+        noalloc the call goes to hc_track_device_noalloc (the library's fixed
+        device workspace, no allocation)."""
         import torch
 
         def dp(t):
@@ -334,9 +340,9 @@ class Context:
                 raise ValueError("per-instance start: start [n_inst, n_start, n] and p_start [n_inst, n_params]")
             o = Opts.from_buffer_copy(o)
             o.per_instance_start = 1
-        _check(lib().hc_track_device(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target),
-                                     n_inst, dp(gamma), ctypes.byref(o), dp(endpoints), dp(status), dp(info),
-                                     ctypes.c_void_p(stream.cuda_stream)))
+        fn = lib().hc_track_device_noalloc if noalloc else lib().hc_track_device
+        _check(fn(self.handle, s.handle, dp(start), n_start, dp(p_start), dp(p_target), n_inst, dp(gamma),
+                  ctypes.byref(o), dp(endpoints), dp(status), dp(info), ctypes.c_void_p(stream.cuda_stream)))
 
     def autotune(self, s: System, p_target, gamma, endpoints, status, info=None, start=None, p_start=None,
                  n_start: Optional[int] = None, opts: Optional[Opts] = None, stream=None) -> Opts:
