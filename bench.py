@@ -156,17 +156,34 @@ def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, us
     return out
 
 
+def has_duplicate(f, tol=1e-8):
+    """Whether two rows of f lie within tol (relative max-norm) of each other."""
+    if len(f) < 2:
+        return False
+    d = np.abs(f[:, None, :] - f[None, :, :]).max(-1) / np.maximum(1.0, np.abs(f).max(-1))[None, :]
+    d[np.arange(len(f)), np.arange(len(f))] = np.inf
+    return bool(d.min() <= tol)
+
+
 def set_parity(ep_g, st_g, ep_o, st_o, ok_gpu=0):
     """Endpoint error of the GPU's finite solutions against the FP64 oracle's,
     instance by instance: a one-to-one pairing (nearest oracle root by k-d tree,
     greedy when two GPU roots pick the same one), relative max-norm distance over
     max(1, |x|).  Returns the worst distance, the instances whose finite counts
-    differ, and the failure rates of both sides."""
+    differ, and the failure rates of both sides.  An instance where two of the
+    oracle's finite endpoints coincide lost a root to path jumping on the oracle's
+    side (it has no crossing check): it is counted apart, as are instances whose
+    GPU endpoints repeat a root."""
     from scipy.spatial import cKDTree
-    worst, mismatch = 0.0, 0
+    worst, mismatch, o_dup, g_dup = 0.0, 0, 0, 0
     for i in range(len(ep_o)):
         fg = ep_g[i][st_g[i] == ok_gpu]
         fo = ep_o[i][st_o[i] == 0]
+        if has_duplicate(fg):
+            g_dup += 1
+        if has_duplicate(fo):
+            o_dup += 1
+            continue
         if len(fg) != len(fo):
             mismatch += 1
             continue
@@ -184,6 +201,7 @@ def set_parity(ep_g, st_g, ep_o, st_o, ok_gpu=0):
         d = np.max(np.abs(fg[j] - fo), axis=1) / np.maximum(1.0, np.max(np.abs(fo), axis=1))
         worst = max(worst, float(d.max()))
     return {"instances": len(ep_o), "max_rel_err": worst, "finite_count_mismatches": mismatch,
+            "oracle_path_jump_instances": o_dup, "gpu_duplicate_instances": g_dup,
             "gpu_failure_rate": float(np.mean(st_g[:len(ep_o)] != ok_gpu)),
             "oracle_failure_rate": float(np.mean(st_o != 0))}
 
@@ -234,13 +252,17 @@ def oracle_sample(S, coef, start, c0, k):
 
 
 def run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S, kernel_fmt,
-                    w_contract, w_kernel, useful_per_step, useful_source, osamp, n_inst, n_start):
+                    w_contract, w_kernel, useful_per_step, useful_source, osamp, n_inst, n_start, osamp_eg=None):
     """FP64 and mixed runs of one parameter-homotopy batch: timing, statuses,
-    roofline, endpoint error on the oracle's sampled instances."""
+    roofline, endpoint error on the oracle's sampled instances; with osamp_eg
+    (the oracle's end-game endpoints of the same sample) also mixed precision
+    with the end-game ("mixed_endgame")."""
     out = {}
-    oep, ost = osamp
-    for mode in ("fp64", "mixed"):
-        opts = hc.default_opts(precision=mode)
+    modes = ("fp64", "mixed") + (("mixed_endgame",) if osamp_eg is not None else ())
+    for mode in modes:
+        oep, ost = osamp_eg if mode == "mixed_endgame" else osamp
+        opts = hc.default_opts(precision="fp64" if mode == "fp64" else "mixed",
+                               endgame=1 if mode == "mixed_endgame" else 0)
         for _ in range(warmup):
             ctx.track_device(sysh, p, None, ep, st, info, start=start, p_start=ps, opts=opts)
         torch.cuda.synchronize()
@@ -256,14 +278,16 @@ def run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, war
         k = len(oep)
         out[mode] = {"ms_per_step": dt * 1e3, "tracks_per_s": n_inst * n_start / dt, "solves_per_s": n_inst / dt,
                      "success_frac": float(np.mean(stn == hc.HC_T_SUCCESS)),
-                     "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(),
+                     "status_counts": np.bincount(stn.ravel(), minlength=8).tolist(),
                      "escalated": int(inf["escalated"].sum()),
                      "mean_steps": float(inf["steps"].mean() + inf["rejects"].mean()),
                      "endpoint_error_vs_oracle": set_parity(ep[:k].cpu().numpy(), stn[:k], oep, ost),
                      "profile": {q: float(np.mean([r[q] for r in profs])) for q in profs[0]},
-                     "roofline": roofline(profs, "fp32" if mode == "mixed" else "fp64",
-                                          kernel_fmt.format("float" if mode == "mixed" else "double"),
+                     "roofline": roofline(profs, "fp64" if mode == "fp64" else "fp32",
+                                          kernel_fmt.format("double" if mode == "fp64" else "float"),
                                           w_contract, w_kernel, useful_per_step, useful_source)}
+        if mode == "mixed_endgame":
+            out[mode]["cycle_counts"] = np.bincount(inf["cycle"].ravel(), minlength=3).tolist()
         log(f"bench: {mode}: {dt * 1e3:.1f} ms/step, {n_inst * n_start / dt:.3e} tracks/s")
     out["mixed_over_fp64"] = round(out["mixed"]["tracks_per_s"] / out["fp64"]["tracks_per_s"], 3)
     return out
@@ -280,6 +304,12 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4, sample=16):
     _, coef, _ = V.vision_workload(f"triang{n_views}_batch4096")
     n_inst, n_start, n = coef.shape[0], sols.shape[0], S.n
     oep, ost, oinfo, odt = oracle_sample(S, coef, sols, c0, sample)
+    osamp_eg = None
+    if n_views == 3:
+        # the end-game leg (3 views: ~6% of the paths stop short of infinity without it)
+        import oracle
+        e, s_, _, _ = oracle.track(S, coef[:sample], start=sols, coef0=c0, kind=oracle.LINEAR, endgame=True)
+        osamp_eg = (e, s_)
     w_c = w_stage_param(S)
     useful = useful_flops(oinfo, n, w_c) / sample * n_inst
     p = torch.from_numpy(coef).to(dev)
@@ -297,7 +327,7 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4, sample=16):
     out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
                                "k_track_terms<0,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
                                f"oracle counters of the first {sample} instances, scaled to {n_inst}",
-                               (oep, ost), n_inst, n_start))
+                               (oep, ost), n_inst, n_start, osamp_eg))
     ctx.free_system(sysh)
     return out
 

@@ -57,7 +57,10 @@ typedef enum {
     HC_T_MAX_STEPS = 3,     /* accepted + rejected steps reached max_steps           */
     HC_T_SINGULAR = 4,      /* exactly singular Jacobian during endpoint refinement  */
     HC_T_NONFINITE = 5,     /* non-finite data (coefficients, start point, tangent)  */
-    HC_T_REFINE_FAILED = 6  /* reached t = 1 but the residual stayed above eta_max   */
+    HC_T_REFINE_FAILED = 6, /* reached t = 1 but the residual stayed above eta_max   */
+    HC_T_SINGULAR_END = 7   /* end-game (opts.endgame): a finite endpoint at which
+                               the path has cycle number >= 2 (a singular root); the
+                               endpoint is the end-game's estimate, not refined     */
 } hc_track_status;
 
 typedef enum {
@@ -79,8 +82,11 @@ typedef struct {
     int32_t rejects;     /* rejected steps                                   */
     int32_t newton_its;  /* corrector iterations while tracking              */
     int32_t refine_its;  /* Newton iterations of the FP64 endpoint refinement */
-    int32_t escalated;   /* 1 if mixed mode handed the path to FP64 tracking */
-    int32_t reserved;
+    int32_t escalated;   /* 1 if the path was tracked in FP64 after starting
+                            otherwise: mixed mode's hand-over, or a re-tracking
+                            by the crossing check or the end-game            */
+    int32_t cycle;       /* end-game cycle number (winding number) of the
+                            path at t = 1; 0 where no end-game converged     */
     double residual;     /* relative backward error max_i |F_i| / sum_k |c_k||m_k|
                             at the endpoint; NaN when t = 1 was not reached */
 } hc_track_info;
@@ -140,7 +146,7 @@ typedef struct {
     int32_t use_graph;        /* hc_track_device: capture the launch sequence in a
                                  hipGraph on the first call and replay it while the
                                  arguments stay the same (needs a non-null stream,
-                                 steps_per_launch 0, profiling off)             (0)     */
+                                 steps_per_launch 0, endgame 0, profiling off)  (0)     */
     int32_t fp64_residual;    /* mixed mode: the FP32 pass's Newton corrector evaluates
                                  H(x, t) in FP64 at an FP64 point (dense tables: from
                                  the FP32 coefficients; term lists: from the FP64
@@ -161,6 +167,34 @@ typedef struct {
                                  the system in that layout, made on first use (an
                                  allocation); HC_E_UNSUPPORTED if that layout
                                  cannot hold the system; 0 = autotuned        (0)     */
+    /* Power-series end-game (not in the paper; Morgan, Sommese and Wampler, Numer.
+     * Math. 63, 1992).  With s = 1 - t a path near t = 1 is a power series in
+     * s^(1/c) for its cycle number c.  A path that fails inside the zone
+     * [1 - eg_s0, 1] (MIN_STEP, MAX_STEPS) or reaches t = 1 without a regular
+     * endpoint (REFINE_FAILED, SINGULAR) is re-tracked in FP64 from its start point
+     * and sampled at s_k = eg_s0 eg_beta^k, k >= 1 (in the zone with corrector
+     * tolerance eg_tau, eg_max_newton iterations, minimum step eg_h_min); the
+     * samples are taken in projective coordinates y = (1, x) / (a . (1, x)) on the
+     * fixed patch a_j = exp(2 pi i frac((j + 1)(sqrt 5 - 1) / 2)), j = 0..n; from
+     * every three in a row c is estimated from the decay of their differences and
+     * y(0) extrapolated by the quadratic in s^(1/c) through them.  The end-game has
+     * converged when two successive estimates agree to eg_tol |y|_inf, or to
+     * eg_tol_inf |y|_inf with y_0 below |y|_inf / inf_bound (a path to infinity).
+     * A converged path then ends AT_INFINITY (|x|_inf > inf_bound), with the usual
+     * FP64 refinement and classification from the estimate (c = 1), or
+     * SINGULAR_END at the estimate (c >= 2); an unconverged one keeps its first
+     * result.  Not available in the batch and server calls. */
+    int32_t endgame;          /* 0 off; 1 on for failed paths; 2 on for every path
+                                 that reaches the zone and met no non-finite value (0) */
+    int32_t eg_max_newton;    /* corrector iterations per step in the zone     (5)     */
+    int32_t eg_max_samples;   /* samples s_1 .. s_K, K <= 64                   (16)    */
+    int32_t eg_max_cycle;     /* largest cycle number                          (8)     */
+    double eg_s0;             /* the zone is [1 - eg_s0, 1]                    (0.1)   */
+    double eg_beta;           /* sample ratio s_(k+1) / s_k                    (0.25)  */
+    double eg_tol;            /* convergence of successive estimates          (1e-9)  */
+    double eg_tol_inf;        /* the same for a path to infinity              (1e-3)  */
+    double eg_tau;            /* corrector tolerance in the zone               (1e-8)  */
+    double eg_h_min;          /* smallest step in the zone                     (1e-14) */
 } hc_opts;
 
 typedef struct hc_ctx hc_ctx;
@@ -244,7 +278,8 @@ hc_status hc_track(hc_ctx *ctx, const hc_system *sys,
 /* Same as hc_track, but every array argument is a device pointer on the
  * context's device, and the work is enqueued on `stream` (a hipStream_t; NULL =
  * the null stream).  Returns once the work is enqueued unless
- * opts->steps_per_launch > 0, which needs host round trips between launches.
+ * opts->steps_per_launch > 0 or opts->endgame is on, which need host round
+ * trips between launches.
  * The outputs are valid after the stream has been synchronised.  The library's
  * workspace is reused by the next call on the same context. */
 hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
@@ -271,9 +306,9 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
  * threads) race and corrupt each other's paths -- serialise them.  Kernels clear
  * what must start at zero themselves, so back-to-back calls on one stream are
  * safe.  Differences from hc_track_device: opts->use_graph is ignored (capture
- * the call instead), profiling is not recorded, and a table_layout other than
- * the system's own is served only if hc_autotune or an earlier call already
- * made that copy.
+ * the call instead), profiling is not recorded, the end-game (opts->endgame) is
+ * not available, and a table_layout other than the system's own is served only
+ * if hc_autotune or an earlier call already made that copy.
  * Errors: as hc_track_device; HC_E_UNSUPPORTED when the workspace exceeds
  * HC_NOALLOC_SCRATCH_BYTES (the message gives both sizes) or the table layout
  * would need a new copy. */
@@ -302,6 +337,18 @@ hc_status hc_track_device_noalloc(hc_ctx *ctx, const hc_system *sys,
  * batch > 0), HC_E_DEVICE. */
 hc_status hc_solve_batched_device(hc_ctx *ctx, int32_t n, int64_t batch, int32_t fp32, const void *A,
                                   const void *b, void *x, int32_t *info, void *stream);
+
+/* Duplicate marking of a point set (the merge step of monodromy, which the paper
+ * uses to compute its start systems, section 7): keep[i] = 1 unless an earlier
+ * point j < i lies within the relative tolerance,
+ *   max_k |x_ik - x_jk| <= tol max(1, |x_i|_inf, |x_j|_inf),
+ * else 0.  Every point is compared with all earlier ones (not only the kept
+ * ones): the two differ only where duplicates chain (a ~ b ~ c with a, c apart).
+ *   points: device [count][n] (hc_c64), n in 1..64;  keep: device [count].
+ * Enqueued on `stream` (NULL = the null stream); allocates nothing.
+ * Errors: HC_E_INVALID, HC_E_DEVICE. */
+hc_status hc_distinct_device(hc_ctx *ctx, int32_t n, int64_t count, const hc_c64 *points, double tol,
+                             int32_t *keep, void *stream);
 
 /* Diagnostic: the measured vector FMA rate of the context's device in TFLOP/s
  * (2 FLOP per FMA), the check of the peak the trackers' ALU roofline is quoted

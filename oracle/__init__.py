@@ -75,7 +75,7 @@ class EgOpts(ctypes.Structure):
 
 
 # The end-game's constants (ours: the paper has no end-game).
-EG_DEFAULTS = dict(s0=0.1, beta=0.25, tol=1e-9, tol_inf=1e-3, tau=1e-10, h_min=1e-14, max_newton=5, max_samples=16,
+EG_DEFAULTS = dict(s0=0.1, beta=0.25, tol=1e-9, tol_inf=1e-3, tau=1e-8, h_min=1e-14, max_newton=5, max_samples=16,
                    max_cycle=8, every=0)
 
 

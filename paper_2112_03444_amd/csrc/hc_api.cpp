@@ -86,6 +86,16 @@ void hc_default_opts(hc_opts *o)
     o->fp64_residual = 0;
     o->crossing_check = 1;
     o->per_instance_start = 0;
+    o->endgame = 0;
+    o->eg_max_newton = 5;
+    o->eg_max_samples = 16;
+    o->eg_max_cycle = 8;
+    o->eg_s0 = 0.1;
+    o->eg_beta = 0.25;
+    o->eg_tol = 1e-9;
+    o->eg_tol_inf = 1e-3;
+    o->eg_tau = 1e-8;
+    o->eg_h_min = 1e-14;
 }
 
 const char *hc_last_error(void) { return last_error(); }
@@ -164,6 +174,7 @@ void hc_destroy(hc_ctx *c)
     c->io.release();
     c->counter.release();
     c->queue.release();
+    c->eg.release();
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->bgraph_exec) (void)hipGraphExecDestroy(c->bgraph_exec);
     for (hipEvent_t &e : c->ev)
@@ -478,6 +489,12 @@ static hc_status check_opts(const hc_opts &o)
         return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4, 8 or 16)", o.lanes_per_path);
     if (o.precision == HC_MIXED && !(o.t_end >= 0 && o.t_end < 1))
         return fail(HC_E_INVALID, "opts.t_end = %g must lie in [0, 1) in mixed mode", o.t_end);
+    if (o.endgame < 0 || o.endgame > 2) return fail(HC_E_INVALID, "opts.endgame = %d (0, 1 or 2)", o.endgame);
+    if (o.endgame &&
+        (!(o.eg_s0 > 0 && o.eg_s0 < 1) || !(o.eg_beta > 0 && o.eg_beta < 1) || !(o.eg_tol > 0) ||
+         !(o.eg_tol_inf >= 0) || !(o.eg_tau > 0) || !(o.eg_h_min >= 0) || o.eg_max_newton < 1 ||
+         o.eg_max_samples < 0 || o.eg_max_samples > kEgMaxSamples || o.eg_max_cycle < 1))
+        return fail(HC_E_INVALID, "opts: end-game values out of range");
     return HC_OK;
 }
 
@@ -583,6 +600,111 @@ static bool mixed_check_big(const hc_opts &o, int n_start)
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The power-series end-game after refinement (opts.endgame): candidates (paths
+// that failed in the zone [1 - eg_s0, 1], or every path there with endgame = 2)
+// are compacted into a list and re-tracked in FP64 from their start points to
+// 1 - eg_s0 with the usual options, then with the zone's options to 1 - s_k for
+// k = 1 .. eg_max_samples, one launch per sample followed by k_eg_sample.  Paths
+// it classifies at infinity are written out by k_eg_sample; finite estimates
+// with cycle number 1 get the usual refinement, those with cycle number >= 2
+// only the classification (HC_T_SINGULAR_END).  Candidates whose end-game does
+// not converge keep the outputs of the first refinement.  Needs one host
+// round trip (the candidate count) and an allocation for the candidates.
+template <typename RunPass>
+static hc_status run_endgame(hc_ctx *c, const hc_system *s, hc_opts &o, long long total, const TrackState &S,
+                             const InitArgs &ia, const RefineArgs &ra, char *counter_p, RunPass &run_pass,
+                             TrackArgs &ta, hipStream_t st)
+{
+    EgArgs ea{};
+    ea.n = s->n;
+    ea.total = total;
+    ea.s = S;
+    ea.mode = o.endgame;
+    ea.s0 = o.eg_s0;
+    ea.beta = o.eg_beta;
+    ea.tol = o.eg_tol;
+    ea.tol_inf = o.eg_tol_inf;
+    ea.inf_bound = o.inf_bound;
+    ea.max_cycle = o.eg_max_cycle;
+    ea.endpoints = ra.endpoints;
+    ea.status = ra.status;
+    ea.info = ra.info;
+    ea.count = reinterpret_cast<unsigned *>(counter_p + 48);
+    HIP_TRY(c->eg.ensure((size_t)total * sizeof(int)));
+    ea.list = static_cast<int *>(c->eg.p);
+    HIP_TRY(launch_fill_u32(ea.count, 0u, 1, st));
+    HIP_TRY(launch_eg_select(ea, st));
+    unsigned m = 0;
+    HIP_TRY(hipMemcpyAsync(&m, ea.count, sizeof m, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (m == 0) return HC_OK;
+    // per candidate: 3 samples + the previous estimate (n + 1 complex each), class, flag
+    const size_t n1 = (size_t)s->n + 1;
+    const size_t list_b = al256((size_t)total * sizeof(int));
+    const size_t ring_b = al256((size_t)3 * m * n1 * 16), prev_b = al256((size_t)m * n1 * 16);
+    const size_t need = list_b + ring_b + prev_b + 2 * al256((size_t)m * sizeof(int));
+    if (need > c->eg.cap) {
+        // grow, keeping the candidate list
+        std::vector<int> keep(m);
+        HIP_TRY(hipMemcpyAsync(keep.data(), c->eg.p, (size_t)m * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(c->eg.ensure(need));
+        HIP_TRY(hipMemcpyAsync(c->eg.p, keep.data(), (size_t)m * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    char *base = static_cast<char *>(c->eg.p);
+    ea.list = reinterpret_cast<int *>(base);
+    ea.ring = reinterpret_cast<double *>(base + list_b);
+    ea.prev = reinterpret_cast<double *>(base + list_b + ring_b);
+    ea.cls = reinterpret_cast<int *>(base + list_b + ring_b + prev_b);
+    ea.have_prev = reinterpret_cast<int *>(base + list_b + ring_b + prev_b + al256((size_t)m * sizeof(int)));
+    ea.m = (int)m;
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned *>(ea.cls), 0u, (int)m, st));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned *>(ea.have_prev), 0u, (int)m, st));
+
+    // re-track the candidates in FP64 to the zone with the usual options
+    InitArgs ir = ia;
+    ir.retrack = 1;
+    HIP_TRY(launch_init(ir, st));
+    hc_status rc = run_pass(false, 1.0 - o.eg_s0, 0);
+    if (rc != HC_OK) return rc;
+    // inside the zone: the end-game's corrector and minimum step
+    const double tau64 = o.tau64, h_min = ta.h_min;
+    const int max_newton = ta.max_newton;
+    o.tau64 = o.eg_tau;
+    ta.h_min = o.eg_h_min;
+    ta.max_newton = o.eg_max_newton;
+    double sk = o.eg_s0;
+    for (int k = 1; k <= o.eg_max_samples && rc == HC_OK; k++) {
+        sk *= o.eg_beta;
+        ea.k = k;
+        ea.t_k = 1.0 - sk;
+        rc = run_pass(false, ea.t_k, 0);
+        if (rc == HC_OK) {
+            const hipError_t e = launch_eg_sample(ea, st);
+            if (e != hipSuccess) rc = fail(HC_E_DEVICE, "launch_eg_sample: %s", hipGetErrorString(e));
+        }
+    }
+    o.tau64 = tau64;
+    ta.h_min = h_min;
+    ta.max_newton = max_newton;
+    if (rc != HC_OK) return rc;
+
+    // cycle number 1: the usual refinement from the estimate; >= 2: classification only
+    RefineArgs r1 = ra;
+    r1.eg_cycle = 1;
+    RefineArgs r2 = r1;
+    r2.max_refine = 0;
+    r2.singular_end = 1;
+    for (int cls = 1; cls <= 2; cls++) {
+        HIP_TRY(launch_eg_mark(ea, cls, st));
+        const RefineArgs &r = cls == 1 ? r1 : r2;
+        if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(s->tk, r, st));
+        else HIP_TRY(launch_refine(s->n, r, st));
+    }
+    return HC_OK;
+}
+
 static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *start, int32_t n_start,
                                    const hc_c64 *p_start, const hc_c64 *p_target, int32_t n_inst,
                                    const hc_c64 *gamma, const hc_opts *opts_in, hc_c64 *endpoints,
@@ -598,6 +720,8 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     if (rc != HC_OK) return rc;
     rc = apply_tuning(c, s, o, n_start, n_inst, !noalloc);
     if (rc != HC_OK) return rc;
+    if (noalloc && o.endgame)
+        return fail(HC_E_UNSUPPORTED, "hc_track_device_noalloc: the end-game allocates its candidate buffers");
     const bool param = s->kind == HC_PARAMETER;
     if (!param && !start && n_start > s->bezout)
         return fail(HC_E_INVALID, "hc_track: n_start = %d exceeds the Bezout number %lld", n_start,
@@ -811,7 +935,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     }
     if (prof) HIP_TRY(hipEventRecord(c->ev[4], st));
 
-    RefineArgs ra;
+    RefineArgs ra{};
     ra.coef = tab64;
     ra.gamma = reinterpret_cast<const double *>(gamma);
     ra.deg2 = s->deg2;
@@ -853,6 +977,10 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(s->tk, ra, st));
         else HIP_TRY(launch_refine(n, ra, st));
     }
+    if (o.endgame) {
+        rc = run_endgame(c, s, o, total, S, ia, ra, counter_p, run_pass, ta, st);
+        if (rc != HC_OK) return rc;
+    }
     if (prof) {
         HIP_TRY(hipEventRecord(c->ev[6], st));
         c->profiled_call = true;
@@ -876,6 +1004,22 @@ hc_status hc_solve_batched_device(hc_ctx *c, int32_t n, int64_t batch, int32_t f
     return HC_OK;
 }
 
+hc_status hc_distinct_device(hc_ctx *c, int32_t n, int64_t count, const hc_c64 *points, double tol, int32_t *keep,
+                             void *stream)
+{
+    clear_error();
+    if (!c) return fail(HC_E_INVALID, "hc_distinct_device: NULL context");
+    if (n < 1 || n > 64 || count < 0 || !(tol >= 0))
+        return fail(HC_E_INVALID, "hc_distinct_device: n = %d (1..64), count = %lld, tol = %g", n, (long long)count,
+                    tol);
+    if (count == 0) return HC_OK;
+    if (!points || !keep) return fail(HC_E_INVALID, "hc_distinct_device: NULL array");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(launch_distinct(n, count, reinterpret_cast<const double *>(points), tol, keep,
+                            static_cast<hipStream_t>(stream)));
+    return HC_OK;
+}
+
 hc_status hc_measure_vector_peak(hc_ctx *c, int32_t fp64, double *tflops)
 {
     clear_error();
@@ -895,7 +1039,7 @@ hc_status hc_track_device(hc_ctx *c, const hc_system *s, const hc_c64 *start, in
     clear_error();
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool graph = c && opts && opts->use_graph && st != nullptr && opts->steps_per_launch == 0 &&
-                       !c->profiling;
+                       opts->endgame == 0 && !c->profiling;
     auto run = [&]() {
         return track_device_impl(c, s, start, n_start, p_start, p_target, n_inst, gamma, opts, endpoints, status,
                                  info, st);
@@ -1358,7 +1502,7 @@ static hc_status track_batch_impl(hc_ctx *c, int32_t n_jobs, const hc_job *jobs,
         const Plan &p = plan[k];
         if (p.total == 0) continue;
         const TrackArgs &ta = c->h_jobs[(size_t)n_jobs + k];
-        RefineArgs ra;
+        RefineArgs ra{};
         ra.coef = static_cast<const double *>(ta.coef);
         ra.gamma = ta.gamma;
         ra.deg2 = p.s->deg2;
@@ -1508,6 +1652,8 @@ hc_status hc_track_batch_device(hc_ctx *c, int32_t n_jobs, const hc_job *jobs, c
     o.steps_per_launch = 0;
     if (o.per_instance_start)
         return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: per_instance_start is not available in a batch");
+    if (o.endgame)
+        return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: the end-game is not available in a batch");
     if (o.table_layout != HC_LAYOUT_AUTO)
         return fail(HC_E_UNSUPPORTED, "hc_track_batch_device: table_layout must be 0 (each job's own)");
     hipStream_t st = static_cast<hipStream_t>(stream);

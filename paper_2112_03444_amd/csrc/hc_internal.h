@@ -139,6 +139,9 @@ struct RefineArgs {
     long long total;
     int max_refine;
     double tau_refine, inf2, eta_max;
+    int eg_cycle;             // end-game pass: info.cycle = the path's cycle number (kept in succ)
+    int singular_end;         // end-game pass: a finite endpoint within the bound ends
+                              //   HC_T_SINGULAR_END whatever its residual
     TrackState s;
     double *endpoints;        // [total][n][2]
     int *status;              // [total]
@@ -148,6 +151,41 @@ struct RefineArgs {
     const void *vars;         //   the slots' variables
     const int *sdeg;          //   and, general degree, the slots' degrees
 };
+
+// Power-series end-game (hc_endgame.hip).  Candidates are compacted into
+// list[0 .. *count); per candidate the last three samples of the path in
+// projective coordinates (n + 1 complex values each) and the previous estimate
+// live in ring / prev, and cls records the outcome: 0 pending or failed, 1 a
+// finite estimate with cycle number 1 (to be refined), 2 a finite estimate with
+// cycle number >= 2, 3 classified at infinity (written out at once).
+constexpr int kEgMaxSamples = 64;
+struct EgArgs {
+    int n;
+    long long total;
+    TrackState s;
+    int mode;                 // 1: failed paths; 2: every path that reached the zone
+    double s0;
+    int *list;                // [total] capacity
+    unsigned *count;          // candidates found by k_eg_select
+    int m;                    // candidates (host copy of *count) for the sampling kernels
+    double *ring;             // [3][m][n + 1][2]
+    double *prev;             // [m][n + 1][2]
+    int *cls;                 // [m]
+    int *have_prev;           // [m]
+    int k;                    // sample index (>= 1)
+    double t_k;               // 1 - s_k
+    double beta, tol, tol_inf, inf_bound;
+    int max_cycle;
+    double *endpoints;        // outputs, for paths classified at infinity
+    int *status;
+    hc_track_info *info;
+};
+// Marks candidates kRetrack (and appends them to list), every other path kDone.
+hipError_t launch_eg_select(const EgArgs &a, hipStream_t st);
+// Takes sample k of every candidate that reached t_k and updates its estimate.
+hipError_t launch_eg_sample(const EgArgs &a, hipStream_t st);
+// Candidates of class `cls` go to refinement (kReached), all others kDone.
+hipError_t launch_eg_mark(const EgArgs &a, int cls, hipStream_t st);
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
 hipError_t launch_init(const InitArgs &a, hipStream_t st);
@@ -197,6 +235,9 @@ hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long
 constexpr size_t kScratchBytes = (size_t)HC_NOALLOC_SCRATCH_BYTES;
 hipError_t scratch_init(int device);
 void *scratch_ptr(int device);
+
+// Duplicate marking of count points of n complex entries (hc_distinct.hip).
+hipError_t launch_distinct(int n, long long count, const double *pts, double tol, int *keep, hipStream_t st);
 
 // Measured vector FMA rate (hc_peak.hip), TFLOP/s.
 hipError_t measure_peak_fma(bool fp64, double *tflops, hipStream_t st);

@@ -738,6 +738,8 @@ __device__ __forceinline__ void refine_body(const RefineArgs &a, int block)
             resid = residual_dense<N>(as_table(cf), x);
             if (big > a.inf2)
                 st = HC_T_AT_INFINITY;
+            else if (a.singular_end)
+                st = HC_T_SINGULAR_END;
             else if (!(resid <= a.eta_max))
                 st = HC_T_REFINE_FAILED;
             else
@@ -759,7 +761,7 @@ __device__ __forceinline__ void refine_body(const RefineArgs &a, int block)
         inf.newton_its = S.nits[g];
         inf.refine_its = rits;
         inf.escalated = S.escal[g] != 0 ? 1 : 0;
-        inf.reserved = 0;
+        inf.cycle = a.eg_cycle ? S.succ[g] : 0;
         inf.residual = resid;
         a.info[g] = inf;
     }

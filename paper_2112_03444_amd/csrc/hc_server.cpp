@@ -355,8 +355,9 @@ hc_status hc_server_create(hc_ctx *ctx, const hc_server_opts *opts, hc_server **
     else hc_server_default_opts(&o);
     if (o.max_inflight < 1 || o.max_inflight > 16 || o.max_batch_requests < 1 || o.hbm_budget <= 0)
         return fail(HC_E_INVALID, "hc_server_create: max_inflight in [1,16], max_batch_requests >= 1, hbm_budget > 0");
-    if (o.opts.steps_per_launch != 0 || o.opts.lanes_per_path == 1)
-        return fail(HC_E_UNSUPPORTED, "hc_server_create: requests run on the batch tracker (steps_per_launch 0)");
+    if (o.opts.steps_per_launch != 0 || o.opts.lanes_per_path == 1 || o.opts.endgame != 0)
+        return fail(HC_E_UNSUPPORTED, "hc_server_create: requests run on the batch tracker (steps_per_launch 0, "
+                                      "no end-game)");
     hc_server *sv = new (std::nothrow) hc_server;
     if (!sv) return fail(HC_E_OOM, "hc_server_create: out of host memory");
     sv->ctx = ctx;

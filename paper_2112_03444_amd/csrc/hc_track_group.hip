@@ -253,6 +253,8 @@ __device__ __forceinline__ void refine_grp_body(const RefineArgs &a, int block)
             res_out = resid;
             if (big > a.inf2)
                 st = HC_T_AT_INFINITY;
+            else if (a.singular_end)
+                st = HC_T_SINGULAR_END;
             else if (!(resid <= a.eta_max))
                 st = HC_T_REFINE_FAILED;
             else
@@ -274,7 +276,7 @@ __device__ __forceinline__ void refine_grp_body(const RefineArgs &a, int block)
             inf.newton_its = S.nits[g];
             inf.refine_its = rits;
             inf.escalated = S.escal[g] != 0 ? 1 : 0;
-            inf.reserved = 0;
+            inf.cycle = a.eg_cycle ? S.succ[g] : 0;
             inf.residual = res_out;
             a.info[g] = inf;
         }

@@ -23,9 +23,9 @@ HC_OK = 0
 HC_TOTAL_DEGREE, HC_PARAMETER = 0, 1
 HC_FP64, HC_MIXED = 0, 1
 (HC_T_SUCCESS, HC_T_AT_INFINITY, HC_T_MIN_STEP, HC_T_MAX_STEPS, HC_T_SINGULAR, HC_T_NONFINITE,
- HC_T_REFINE_FAILED) = range(7)
+ HC_T_REFINE_FAILED, HC_T_SINGULAR_END) = range(8)
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
-                "REFINE_FAILED"]
+                "REFINE_FAILED", "SINGULAR_END"]
 HC_MAX_N = 20
 HC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed workspace of hc_track_device_noalloc, per device
 HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
@@ -52,7 +52,10 @@ class Opts(ctypes.Structure):
                [(k, ctypes.c_int32) for k in
                 ("precision", "n_inc", "max_newton", "max_steps", "max_refine",
                  "steps_per_launch", "tracks_per_item", "lanes_per_path", "use_graph", "fp64_residual",
-                 "crossing_check", "per_instance_start", "table_layout")]
+                 "crossing_check", "per_instance_start", "table_layout", "endgame", "eg_max_newton",
+                 "eg_max_samples", "eg_max_cycle")] + \
+               [(k, ctypes.c_double) for k in
+                ("eg_s0", "eg_beta", "eg_tol", "eg_tol_inf", "eg_tau", "eg_h_min")]
 
 
 class Job(ctypes.Structure):
@@ -74,7 +77,7 @@ class Profile(ctypes.Structure):
 
 
 INFO_DTYPE = np.dtype([("steps", np.int32), ("rejects", np.int32), ("newton_its", np.int32),
-                       ("refine_its", np.int32), ("escalated", np.int32), ("reserved", np.int32),
+                       ("refine_its", np.int32), ("escalated", np.int32), ("cycle", np.int32),
                        ("residual", np.float64)])
 assert INFO_DTYPE.itemsize == 32
 
@@ -137,6 +140,8 @@ def lib():
         L.hc_solve_batched_device.argtypes = [P, I32, I64, I32, P, P, P, P, P]
         L.hc_measure_vector_peak.restype = ctypes.c_int
         L.hc_measure_vector_peak.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
+        L.hc_distinct_device.restype = ctypes.c_int
+        L.hc_distinct_device.argtypes = [P, I32, I64, P, ctypes.c_double, P, P]
         L.hc_homogenize.restype = ctypes.c_int
         L.hc_homogenize.argtypes = [I32, I32, P, P, P, P, I32, I32, P]
         _lib = L
@@ -435,6 +440,19 @@ class Context:
                                              ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                              None if info is None else ctypes.c_void_p(info.data_ptr()),
                                              ctypes.c_void_p(stream.cuda_stream)))
+
+    def distinct_device(self, points, tol: float = 1e-8, stream=None):
+        """hc_distinct_device on a complex128 torch tensor [count, n]: the int32
+        keep mask (1 = no earlier point within tol)."""
+        import torch
+        pts = points.contiguous()
+        keep = torch.empty(pts.shape[0], dtype=torch.int32, device=pts.device)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().hc_distinct_device(self.handle, pts.shape[1], pts.shape[0], ctypes.c_void_p(pts.data_ptr()),
+                                        float(tol), ctypes.c_void_p(keep.data_ptr()),
+                                        ctypes.c_void_p(stream.cuda_stream)))
+        return keep
 
     def measure_vector_peak(self, fp64: bool) -> float:
         """hc_measure_vector_peak: the device's measured FMA rate in TFLOP/s

@@ -6,7 +6,8 @@ Numer. Anal. 2019).
 1. A fabricated exact pair (p0, x0): x0 solves the instance p0.
 2. Loops p0 -> pa -> pb -> p0 over random complex parameter points carry every
    known solution around; distinct new endpoints join the set (closed under
-   the family's known symmetries).
+   the family's known symmetries).  The merge runs on the device
+   (hc_distinct_device).
 3. Stop after `stall` loops without growth, at `target` solutions, or after
    `max_loops`.
 
@@ -101,13 +102,25 @@ def distinct(sols: np.ndarray, tol: float = 1e-8) -> np.ndarray:
     return sols[keep]
 
 
-def _close(sols, orbit, tol):
+def distinct_on_device(ctx, sols: np.ndarray, tol: float = 1e-8) -> np.ndarray:
+    """`distinct` by the library's device kernel (hc_distinct_device): a row is
+    dropped when any earlier row lies within tol (the host version compares with
+    the kept rows only; the two differ only where near-duplicates chain)."""
+    import torch
+    sols = np.asarray(sols, np.complex128)
+    if len(sols) <= 1:
+        return sols
+    keep = ctx.distinct_device(torch.from_numpy(np.ascontiguousarray(sols)).to("cuda"), tol)
+    return sols[keep.cpu().numpy().astype(bool)]
+
+
+def _close(sols, orbit, tol, dedup=distinct):
     if orbit is None or len(sols) == 0:
         return sols
     imgs = orbit(sols)
     if imgs is None:
         return sols
-    return distinct(np.concatenate([sols, np.asarray(imgs).reshape(-1, sols.shape[1])]), tol)
+    return dedup(np.concatenate([sols, np.asarray(imgs).reshape(-1, sols.shape[1])]), tol)
 
 
 def _path(ctx, handle, family, p_from, p_to, sols, opts):
@@ -130,7 +143,11 @@ def monodromy(ctx, family, seed: int = 0, stall: int = 10, max_loops: int = 500,
     opts = _hc.default_opts(precision=precision)
     rng = np.random.default_rng(seed)
     p0, x0 = family.fabricate(rng)
-    sols = _close(np.asarray(x0)[None, :], family.orbit, tol)
+
+    def dedup(x, tl):
+        return distinct_on_device(ctx, x, tl)
+
+    sols = _close(np.asarray(x0)[None, :], family.orbit, tol, dedup)
     quiet = 0
     t0 = time.time()
     try:
@@ -139,7 +156,8 @@ def monodromy(ctx, family, seed: int = 0, stall: int = 10, max_loops: int = 500,
             xa = _path(ctx, handle, family, p0, pa, sols, opts)
             xb = _path(ctx, handle, family, pa, pb, xa, opts)
             back = _path(ctx, handle, family, pb, p0, xb, opts)
-            merged = _close(distinct(np.concatenate([sols, back]), tol), family.orbit, tol) if len(back) else sols
+            merged = _close(dedup(np.concatenate([sols, back]), tol), family.orbit, tol, dedup) if len(back) \
+                else sols
             grew = len(merged) - len(sols)
             sols = merged
             quiet = 0 if grew > 0 else quiet + 1
