@@ -206,6 +206,40 @@ def set_parity(ep_g, st_g, ep_o, st_o, ok_gpu=0):
             "oracle_failure_rate": float(np.mean(st_o != 0))}
 
 
+def trifocal_slack(S) -> float:
+    """Factor on an FP64 root's first-order forward-error bound for the distance
+    of two correct FP64 computations of it: 2 (2 sqrt(2) (d + 1) + T_i) for terms
+    of degree <= d in T_i terms per equation (the evaluation's rounding, twice)."""
+    d = int(np.asarray(S.term_exp).sum(axis=1).max())
+    T = int(np.bincount(np.asarray(S.term_eq)).max())
+    return 2.0 * (2.0 * np.sqrt(2.0) * (d + 1) + T)
+
+
+def conditioned_parity(ep_g, st_g, ep_o, st_o, fe_o, slack, rel=1e-9):
+    """For badly conditioned roots (trifocal): per instance the one-to-one
+    pairing's distances against each oracle root's own bar max(rel, slack x its
+    forward-error bound + 2e-14); returns the roots past rel, those past their
+    own bar, and the worst distance over the bound."""
+    from scipy.spatial import cKDTree
+    past_rel = past_bar = 0
+    worst = 0.0
+    for i in range(len(ep_o)):
+        fg = ep_g[i][st_g[i] == 0]
+        ok = st_o[i] == 0
+        fo, fe = ep_o[i][ok], fe_o[i][ok]
+        if len(fg) != len(fo) or len(fo) == 0:
+            continue
+        emb = lambda z: np.concatenate([z.real, z.imag], axis=1)  # noqa: E731
+        _, j = cKDTree(emb(fg)).query(emb(fo), k=1, p=np.inf)
+        d = np.max(np.abs(fg[j] - fo), axis=1) / np.maximum(1.0, np.max(np.abs(fo), axis=1))
+        bar = slack * fe + 2e-14
+        past_rel += int(np.sum(d > rel))
+        past_bar += int(np.sum(d > np.maximum(rel, bar)))
+        worst = max(worst, float(np.max(d / bar)))
+    return {"slack": round(slack, 2), "roots_past_1e-9": past_rel, "roots_past_own_bar": past_bar,
+            "worst_distance_over_bound": worst}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -477,12 +511,16 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_fp64=256):
                "finite_per_instance": float(np.mean(np.sum(stn == hc.HC_T_SUCCESS, axis=1))),
                "status_counts": np.bincount(stn.ravel(), minlength=7).tolist(), "legs": legs}
         if gold is not None:
-            idx = [int(i) for i in gold["instances"] if i < ni]
+            sel = [k for k, i in enumerate(gold["instances"]) if int(i) < ni]
+            idx = [int(gold["instances"][k]) for k in sel]
             if idx:
                 epn = ep[:ni].cpu().numpy()
-                res["endpoint_error_vs_oracle"] = set_parity(epn[idx], stn[idx], gold["endpoints"][:len(idx)],
-                                                             gold["status"][:len(idx)])
+                res["endpoint_error_vs_oracle"] = set_parity(epn[idx], stn[idx], gold["endpoints"][sel],
+                                                             gold["status"][sel])
                 res["endpoint_error_vs_oracle"]["instances_checked"] = idx
+                res["endpoint_error_vs_oracle"]["conditioned"] = conditioned_parity(
+                    epn[idx], stn[idx], gold["endpoints"][sel], gold["status"][sel], gold["fe_bound"][sel],
+                    trifocal_slack(S))
             # per leg, the oracle's tracking FLOPs of its sampled instances, scaled
             # to this run's instances; a "launch" here is one leg
             # one call = one leg: half the two legs' work per call on average

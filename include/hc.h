@@ -142,7 +142,11 @@ typedef struct {
     int32_t tracks_per_item;  /* paths per wavefront work item, 0 = autotuned  (0)     */
     int32_t lanes_per_path;   /* 1: one path per lane; 4 or 8: one row of [H_x | rhs]
                                  per lane, 4 or 8 lanes per path (dense tables);
-                                 term lists take 16 (n <= 16) or 32; 0 = autotuned (0)  */
+                                 term lists take 16 (n <= 16) or 32; 64: one path
+                                 per wavefront, one entry of H_x per lane (dense
+                                 total-degree tables, 2 <= n <= 8, FP64 only: the
+                                 short-latency layout the crossing check's and the
+                                 end-game's re-tracking use); 0 = autotuned   (0)     */
     int32_t use_graph;        /* hc_track_device: capture the launch sequence in a
                                  hipGraph on the first call and replay it while the
                                  arguments stay the same (needs a non-null stream,
@@ -297,7 +301,8 @@ hc_status hc_track_device(hc_ctx *ctx, const hc_system *sys,
  * library from load until the process ends; the call makes no hipMalloc,
  * hipFree or other allocation.  Workspace of one call, in bytes (each part
  * rounded up to 256): 256 + n_inst n_start (16 n + 40) [+ 16 n_inst n_start in
- * mixed precision with n_start > 8192] + (n_inst + P) n T (16, + 8 in mixed
+ * mixed precision with n_start > 8192] [+ 4 n_inst n_start for dense
+ * total-degree tables with 2 <= n <= 8] + (n_inst + P) n T (16, + 8 in mixed
  * precision), where T is the system's table slots per equation and P is 0 for
  * total degree, 1 for HC_PARAMETER (n_inst with per_instance_start); the
  * dense n = 8 batch of 512 x 256 paths takes about 27 MB.

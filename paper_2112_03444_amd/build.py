@@ -22,7 +22,8 @@ SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp")
            os.path.join(CSRC, "hc_terms_q16.hip"), os.path.join(CSRC, "hc_terms_g16.hip"),
            os.path.join(CSRC, "hc_terms_g20.hip"), os.path.join(CSRC, "hc_lu.hip"),
            os.path.join(CSRC, "hc_peak.hip"), os.path.join(CSRC, "hc_scratch.hip"),
-           os.path.join(CSRC, "hc_endgame.hip"), os.path.join(CSRC, "hc_distinct.hip")]
+           os.path.join(CSRC, "hc_endgame.hip"), os.path.join(CSRC, "hc_distinct.hip"),
+           os.path.join(CSRC, "hc_wave.hip")]
 ARCH = "gfx950"
 
 

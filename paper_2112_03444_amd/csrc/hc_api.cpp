@@ -485,8 +485,8 @@ static hc_status check_opts(const hc_opts &o)
     if (o.table_layout != HC_LAYOUT_AUTO && o.table_layout != HC_LAYOUT_DENSE && o.table_layout != HC_LAYOUT_TERMS)
         return fail(HC_E_INVALID, "opts.table_layout = %d", o.table_layout);
     if (o.lanes_per_path != 0 && o.lanes_per_path != 1 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
-        o.lanes_per_path != 16)
-        return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4, 8 or 16)", o.lanes_per_path);
+        o.lanes_per_path != 16 && o.lanes_per_path != 64)
+        return fail(HC_E_INVALID, "opts.lanes_per_path = %d (0, 1, 4, 8, 16 or 64)", o.lanes_per_path);
     if (o.precision == HC_MIXED && !(o.t_end >= 0 && o.t_end < 1))
         return fail(HC_E_INVALID, "opts.t_end = %g must lie in [0, 1) in mixed mode", o.t_end);
     if (o.endgame < 0 || o.endgame > 2) return fail(HC_E_INVALID, "opts.endgame = %d (0, 1 or 2)", o.endgame);
@@ -507,8 +507,16 @@ constexpr int kRefSlots = kMaxN + 1 + kTermKindCount;
 // n <= 4, 8 for n <= 8; term lists: 16, or 32 for n > 16) unless one path per
 // lane is asked for (dense tables) or n = 1.  -1: the option does not fit the
 // system.
+// The one-path-per-wavefront tracker (hc_wave.hip) holds dense total-degree
+// systems with 2 <= n <= 8 in FP64.
+static bool wave_fits(const hc_system *s)
+{
+    return s->layout == HC_LAYOUT_DENSE && s->kind == HC_TOTAL_DEGREE && s->n >= 2 && s->n <= 8;
+}
+
 static int choose_lanes_per_path(const hc_opts &o, const hc_system *s)
 {
+    if (o.lanes_per_path == 64) return wave_fits(s) && o.precision == HC_FP64 ? 64 : -1;
     if (s->layout == HC_LAYOUT_TERMS) {
         const int g = term_kind_lanes(s->tk);
         return (o.lanes_per_path == 0 || o.lanes_per_path == g) ? g : -1;
@@ -666,7 +674,7 @@ static hc_status run_endgame(hc_ctx *c, const hc_system *s, hc_opts &o, long lon
     InitArgs ir = ia;
     ir.retrack = 1;
     HIP_TRY(launch_init(ir, st));
-    hc_status rc = run_pass(false, 1.0 - o.eg_s0, 0);
+    hc_status rc = run_pass(false, 1.0 - o.eg_s0, 0, true);
     if (rc != HC_OK) return rc;
     // inside the zone: the end-game's corrector and minimum step
     const double tau64 = o.tau64, h_min = ta.h_min;
@@ -679,7 +687,7 @@ static hc_status run_endgame(hc_ctx *c, const hc_system *s, hc_opts &o, long lon
         sk *= o.eg_beta;
         ea.k = k;
         ea.t_k = 1.0 - sk;
-        rc = run_pass(false, ea.t_k, 0);
+        rc = run_pass(false, ea.t_k, 0, true);
         if (rc == HC_OK) {
             const hipError_t e = launch_eg_sample(ea, st);
             if (e != hipSuccess) rc = fail(HC_E_DEVICE, "launch_eg_sample: %s", hipGetErrorString(e));
@@ -744,7 +752,11 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const size_t st_ints = (size_t)total * 6;
     const bool big_check = mixed_check_big(o, n_start);
     const size_t proj_off = al256(st_doubles * 8 + st_ints * 4);
-    const size_t state_bytes = big_check ? proj_off + (size_t)total * 16 : st_doubles * 8 + st_ints * 4;
+    const size_t state_core = big_check ? proj_off + (size_t)total * 16 : st_doubles * 8 + st_ints * 4;
+    // dense total-degree systems: the list of paths the one-path-per-wavefront
+    // tracker re-tracks (4 bytes per path)
+    const size_t wave_off = al256(state_core);
+    const size_t state_bytes = wave_fits(s) ? wave_off + (size_t)total * 4 : state_core;
     // tables: n_inst target instances (+ the start instance(s) of a parameter homotopy)
     const bool pis = o.per_instance_start != 0;
     const int n_tab = n_inst + (param ? (pis ? n_inst : 1) : 0);
@@ -881,7 +893,11 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     const int wpb = 4;
 
     // one pass = launches until no path is left suspended by steps_per_launch
-    auto run_pass = [&](bool fp32, double t_final, int escalate) -> hc_status {
+    // few = true: a pass over a few paths (re-tracking after the crossing check,
+    // the end-game), which the one-path-per-wavefront tracker runs at a shorter
+    // stage latency where it holds the system
+    auto run_pass = [&](bool fp32, double t_final, int escalate, bool few) -> hc_status {
+        const bool wave = !fp32 && wave_fits(s) && (few || lanes == 64);
         ta.coef = fp32 ? (const void *)tab32 : (const void *)tab64;
         ta.coef0 = !param ? nullptr : fp32 ? (const void *)tab32_start : (const void *)tab64_start;
         ta.coef0_stride = (param && pis) ? (long long)n_slots * 2 : 0;
@@ -894,10 +910,16 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         ta.escalate = escalate;
         ta.ir = fp32 && o.fp64_residual ? 1 : 0;
         ta.launch_steps = o.steps_per_launch;
-        ta.stage_count = !prof ? nullptr : lanes == 1 ? stage_ctr + (fp32 ? 0 : 1) : stage_ctr;
+        // the lane tracker sums into one counter, the group and wave trackers into
+        // [FP32, FP64]
+        ta.stage_count = !prof ? nullptr : (lanes == 1 && !wave) ? stage_ctr + (fp32 ? 0 : 1) : stage_ctr;
         for (;;) {
             if (o.steps_per_launch > 0) HIP_TRY(hipMemsetAsync(ta.n_suspended, 0, sizeof(unsigned), st));
-            if (lanes == 1) {
+            if (wave) {
+                HIP_TRY(launch_track_wave(n, ta, reinterpret_cast<int *>(state_p + wave_off),
+                                          reinterpret_cast<unsigned *>(counter_p + 56),
+                                          (int)std::min<long long>(total, 4096), st));
+            } else if (lanes == 1) {
                 HIP_TRY(launch_track(n, fp32, ta, wpb, st));
             } else {
                 HIP_TRY(launch_fill_u32(ta.head, 0u, 1, st));
@@ -917,7 +939,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
     if (lanes > 1 && mixed && kInlineEsc) {
         // group tracker: one launch; failed paths and the end zone go on in FP64
         // inside the kernel
-        rc = run_pass(true, 1.0, 0);
+        rc = run_pass(true, 1.0, 0, false);
         if (rc != HC_OK) return rc;
         c->had_fp32 = true;
         if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
@@ -925,12 +947,12 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         // an FP32 pass to 1 - t_end that hands its failures back, then the FP64
         // pass
         if (mixed) {
-            rc = run_pass(true, 1.0 - o.t_end, 1);
+            rc = run_pass(true, 1.0 - o.t_end, 1, false);
             if (rc != HC_OK) return rc;
             c->had_fp32 = true;
         }
         if (prof) HIP_TRY(hipEventRecord(c->ev[3], st));
-        rc = run_pass(false, 1.0, 0);
+        rc = run_pass(false, 1.0, 0, false);
         if (rc != HC_OK) return rc;
     }
     if (prof) HIP_TRY(hipEventRecord(c->ev[4], st));
@@ -972,7 +994,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         InitArgs ir = ia;
         ir.retrack = 1;
         HIP_TRY(launch_init(ir, st));
-        rc = run_pass(false, 1.0, 0);
+        rc = run_pass(false, 1.0, 0, true);
         if (rc != HC_OK) return rc;
         if (s->layout == HC_LAYOUT_TERMS) HIP_TRY(launch_refine_terms(s->tk, ra, st));
         else HIP_TRY(launch_refine(n, ra, st));

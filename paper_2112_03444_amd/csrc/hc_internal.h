@@ -236,6 +236,12 @@ constexpr size_t kScratchBytes = (size_t)HC_NOALLOC_SCRATCH_BYTES;
 hipError_t scratch_init(int device);
 void *scratch_ptr(int device);
 
+// One path per wavefront, one Jacobian entry per lane (hc_wave.hip): dense
+// total-degree tables, 2 <= n <= 8, FP64.  The RUNNING paths below a.t_final
+// are compacted into list ([a.total] capacity; *count is cleared first) and
+// `waves` wavefronts track them, one path each while there are no more.
+hipError_t launch_track_wave(int n, const TrackArgs &a, int *list, unsigned *count, int waves, hipStream_t st);
+
 // Duplicate marking of count points of n complex entries (hc_distinct.hip).
 hipError_t launch_distinct(int n, long long count, const double *pts, double tol, int *keep, hipStream_t st);
 

@@ -81,6 +81,36 @@ def test_dense_fp64_each_n(hc, ctx, n, lanes):
     ctx.free_system(sysh)
 
 
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8])
+def test_dense_fp64_one_path_per_wavefront(hc, ctx, n):
+    """lanes_per_path = 64: one path per wavefront, one Jacobian entry per lane
+    (the layout the crossing check's and the end-game's re-tracking use): set
+    parity with the oracle, and the same roots as the group layout path by path
+    wherever both succeed (same start point, same stage machine)."""
+    S, coef, gam = hc_inputs.dense_quadratic_instances(n, 3, seed=1100 + n)
+    sysh = ctx.load_system(S)
+    ep, st, info = ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=64))
+    ep0, st0, _ = ctx.track(sysh, coef, gam)
+    oep, ost, oinfo = oracle.track(S, coef, gam)
+    for i in range(3):
+        check_instance_parity(ep[i], st[i], oep[i], ost[i], hc)
+    both = (st == hc.HC_T_SUCCESS) & (st0 == hc.HC_T_SUCCESS)
+    d = np.max(np.abs(ep - ep0), axis=-1) / np.maximum(1.0, np.abs(ep0).max(-1))
+    assert d[both].max() <= 1e-9
+    assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-12)
+    # the step sequence follows the oracle's (FP64 both, same control)
+    assert np.mean(info["steps"] == oinfo["steps"]) >= 0.9
+    ctx.free_system(sysh)
+
+
+def test_one_path_per_wavefront_refused_outside_its_range(hc, ctx):
+    S, coef, gam = hc_inputs.dense_quadratic_instances(3, 1, seed=1200)
+    sysh = ctx.load_system(S)
+    with pytest.raises(hc.HcError):
+        ctx.track(sysh, coef, gam, opts=hc.default_opts(lanes_per_path=64, precision="mixed"))
+    ctx.free_system(sysh)
+
+
 @pytest.mark.parametrize("lanes,ir", [(0, 0), (0, 1), (1, 0)])
 @pytest.mark.parametrize("n", [3, 6, 8])
 def test_mixed_mode_residual_and_sets(hc, ctx, n, lanes, ir):
