@@ -145,3 +145,29 @@ def test_noise_free_ground_truth_is_among_the_oracle_endpoints(start):
     for x in TF.symmetry_orbit(sc["gt"][0]):
         d = np.max(np.abs(ok - x), axis=1)
         assert d.min() < 1e-8, d.min()
+
+
+def test_start_set_complete_by_an_independent_run(start):
+    """Completeness of the stored set (no trace test applies to these fibers):
+    an independent monodromy run of the oracle -- its own fabricated start pair
+    (seed 5), its own parameter point and loops, to the same stall rule -- stops
+    at the same count, and each set carried along the two legs to the other
+    run's parameter point lands only on roots of the other set (every path that
+    does not fail tracking reaches a distinct root of the other set).  Written by
+    `python -m oracle.monodromy trifocal-check` and `trifocal-compare`."""
+    import os
+    S = TF.trifocal_system()
+    p0, sols = start
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "trifocal_check.npz"))
+    rep = {str(k): int(v) for k, v in zip(z["compare_keys"], z["compare"])}
+    chk = z["solutions"]
+    assert len(chk) == len(sols) == rep["n_start"] == rep["n_check"]
+    assert not np.allclose(z["params0"], p0)                      # another parameter point
+    assert max(oracle.residual(S, TF.coefficients(z["params0"]), x) for x in chk) < 1e-12
+    assert len(M.distinct_rows(chk, M.TRIFOCAL_MERGE_TOL)) == len(chk)
+    # carried sets: nothing outside the other set; what is missing is exactly
+    # the paths lost on the way
+    assert rep["carried_not_in_start"] == 0 and rep["carried_not_in_check"] == 0
+    assert rep["check_carried"] + rep["start_roots_not_reached"] == len(sols)
+    assert rep["start_carried"] + rep["check_roots_not_reached"] == len(chk)
+    assert rep["start_roots_not_reached"] <= 0.05 * len(sols) and rep["check_roots_not_reached"] <= 0.05 * len(chk)
