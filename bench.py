@@ -26,8 +26,7 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks (FP32: packed)
-SCALAR_FP32_TFLOPS = 78.6                      # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz, one value per lane
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
 # HBM bytes per tracking launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch, scaled by the
 # reading of a 512 MiB device copy in the same run), for the kernel versions profiled in profiles/; they are
 # not measured live, and a kernel changed since its counters were taken has no entry.
@@ -151,8 +150,6 @@ def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, us
            "flops_source": src, "flops_per_stage": w_contract, "useful_flops_per_launch": flops / launches,
            "gpu_stages_per_launch": stages / launches, "flops_per_stage_kernel": w_kernel,
            "achieved_kernel_count": round(stages * w_kernel / launches / per_launch_s / 1e12, 3)}
-    if key == "fp32":
-        out["frac_scalar_fp32"] = round(achieved / SCALAR_FP32_TFLOPS, 4)
     return out
 
 
@@ -582,6 +579,59 @@ def lu_leg(ctx, hc, torch, sizes=(4, 8, 12, 16, 20), batches=(1000, 1 << 18), re
     return out
 
 
+def eval_leg(ctx, hc, torch, repeats=(1, 32), reps=20):
+    """The evaluation step alone on the dense8_batch512 shape (512 instances of
+    the dense n = 8 quadratic family, 256 points each): F and its Jacobian in
+    FP32 by the two engines of hc_eval_dense_device, one Jacobian row per lane
+    on the vector ALUs (the trackers' evaluation) and the [n^2 x (n + 1)] x
+    [(n + 1) x points] matrix-core contraction.  repeat = 1 is bound by the
+    outputs' HBM traffic (8 n (n + 2) bytes per point, read 8 n); repeat = 32
+    evaluates every point 32 times to time the arithmetic.  FLOPs per point and
+    evaluation: 8 n^3 + 16 n^2 (the rows' n^2 complex products of coefficients
+    and unknowns, the linear terms' and Euler's 2n per row).  HIP events on the
+    launch stream, mean of `reps` calls."""
+    import hc_inputs
+    S, coef, _ = hc_inputs.workload("dense8_batch512")
+    n, n_inst, n_pts = S.n, coef.shape[0], 256
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(11)
+    xr = rng.standard_normal((n_inst, n_pts, n, 2)).astype(np.float32)
+    x = torch.from_numpy((xr[..., 0] + 1j * xr[..., 1]).astype(np.complex64)).to(dev)
+    p = torch.from_numpy(coef).to(dev)
+    sysh = ctx.load_system(S, layout=hc.HC_LAYOUT_DENSE)
+    F = torch.empty((n_inst, n_pts, n), dtype=torch.complex64, device=dev)
+    J = torch.empty((n_inst, n_pts, n, n), dtype=torch.complex64, device=dev)
+    w = 8 * n ** 3 + 16 * n ** 2
+    out = {"workload": f"dense8_batch512 shape: {n_inst} instances x {n_pts} points, n={n}, FP32",
+           "flops_per_point": w}
+    for engine, name, peak in ((hc.HC_EVAL_ROWS, "rows_valu", 78.6), (hc.HC_EVAL_MFMA, "mfma", 157.3)):
+        for rep in repeats:
+            def call():
+                ctx.eval_dense_device(sysh, p, x, engine=engine, repeat=rep, F=F, J=J)
+            call()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tf = n_inst * n_pts * rep * w / (ms * 1e-3) / 1e12
+            gbs = n_inst * n_pts * 8 * (n * (n + 2) + n) / (ms * 1e-3) / 1e9
+            out[f"{name}_repeat{rep}"] = {"us": round(ms * 1e3, 2), "TFLOP_per_s": round(tf, 2),
+                                          "frac_of_peak": round(tf / peak, 4), "peak": peak,
+                                          "GB_per_s": round(gbs, 1)}
+            log(f"bench: evaluation {name} repeat {rep}: {ms * 1e3:.1f} us, {tf:.1f} TFLOP/s")
+    Fr, Jr = ctx.eval_dense_device(sysh, p, x, engine=hc.HC_EVAL_ROWS)
+    Fm, Jm = ctx.eval_dense_device(sysh, p, x, engine=hc.HC_EVAL_MFMA)
+    torch.cuda.synchronize()
+    out["max_rel_diff_engines"] = float(((Jr - Jm).abs() / Jr.abs().clamp(min=1.0)).max())
+    out["note"] = ("peaks: 78.6 TFLOP/s for one FP32 value per lane on the vector ALUs (packed FP32 is not "
+                   "used), 157.3 for FP32 matrix cores; GB/s counts x read, F and J written")
+    return out
+
+
 def _serving_trace(rate, total, seed):
     """Open-loop Poisson arrival times over `total` seconds and each request's
     draw (kind, n, instance index), the same for every serving run."""
@@ -695,7 +745,7 @@ def main():
                     help="instances of the trifocal leg's mixed batch (the full batch is 1024)")
     ap.add_argument("--skip", default="",
                     help="comma-separated legs to skip: per_instance,host,latency,triangulation,triangulation3,p3p,"
-                         "fivept,trifocal,lu,serving,serving_per_request")
+                         "fivept,trifocal,lu,eval,serving,serving_per_request")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -769,6 +819,11 @@ def main():
     extras["measured_peak_tflops"] = {"fp32_plain": round(ctx.measure_vector_peak(False), 2),
                                       "fp64": round(ctx.measure_vector_peak(True), 2)}
     log(f"bench: measured vector FMA peaks (TFLOP/s): {extras['measured_peak_tflops']}")
+    # the tracking launches against the FMA rates measured on this device
+    for mode, r in res.items():
+        m = extras["measured_peak_tflops"]["fp32_plain" if mode == "mixed" else "fp64"]
+        if m > 0:
+            r["roofline"]["frac_of_measured_fma_rate"] = round(r["roofline"]["achieved"] / m, 4)
     skip = set(x for x in args.skip.split(",") if x)
     if not args.no_extras and "per_instance" not in skip:
         # paper-style comparator: plain FP64, one instance per call (one launch set each)
@@ -868,6 +923,9 @@ def main():
     if not args.no_extras and "lu" not in skip:
         log("bench: standalone batched LU solves")
         extras["batched_lu"] = lu_leg(ctx, hc, torch)
+    if not args.no_extras and "eval" not in skip:
+        log("bench: evaluation engines (vector rows vs matrix cores) on the dense8_batch512 shape")
+        extras["eval_engines"] = eval_leg(ctx, hc, torch)
     if not args.no_extras and "serving" not in skip:
         log("bench: serving, Poisson arrivals at 2000 requests/s, 1 s warmup + 5 s, mixed and FP64")
         extras["serving"] = serve_mix(ctx, hc)
@@ -899,7 +957,6 @@ def main():
         "cpu_baseline": cpu,
         "modes": {m: {k: v for k, v in r.items() if k != "roofline"} | {"roofline": r["roofline"]}
                   for m, r in res.items()},
-        "peak_scalar_fp32_tflops": SCALAR_FP32_TFLOPS,
     }
     if "mixed" in res and "fp64" in res:
         out["mixed_over_fp64"] = round(res["mixed"]["tracks_per_s"] / res["fp64"]["tracks_per_s"], 3)

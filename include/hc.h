@@ -343,6 +343,35 @@ hc_status hc_track_device_noalloc(hc_ctx *ctx, const hc_system *sys,
 hc_status hc_solve_batched_device(hc_ctx *ctx, int32_t n, int64_t batch, int32_t fp32, const void *A,
                                   const void *b, void *x, int32_t *info, void *stream);
 
+/* Batched evaluation of a dense quadratic system and its Jacobian, FP32: the
+ * evaluation step every tracking stage runs (section 3, Eq. (3)-(4): the
+ * predictor and corrector need H and H_x; section 6: evaluation in parallel),
+ * here of the target system F alone, at n_pts points of each of n_inst
+ * instances.  Two engines compute the same numbers:
+ *   HC_EVAL_ROWS (0): one Jacobian row per lane on the vector ALUs, the
+ *       coefficients read from LDS (the trackers' own evaluation);
+ *   HC_EVAL_MFMA (1): per instance, the n^2 x (n + 1) complex matrix of the
+ *       rows' coefficients times the points' (x, 1) as FP32 matrix-core tiles
+ *       (v_mfma_f32_16x16x4_f32; 16 points per wavefront), F by Euler's
+ *       identity from the rows.
+ *   sys:      a dense-table system (HC_LAYOUT_DENSE), 1 <= n <= 8
+ *   p_target: device [n_inst][n_params] (hc_c64): each instance's coefficients
+ *             or parameters, as in hc_track_device
+ *   x:        device [n_inst][n_pts][n] complex FP32 (interleaved float pairs)
+ *   F:        device [n_inst][n_pts][n] complex FP32: F_r(x)
+ *   J:        device [n_inst][n_pts][n][n] complex FP32: dF_r / dx_a at r n + a
+ *   repeat:   >= 1; every point is evaluated this many times and the outputs are
+ *             one evaluation's (more than 1 only to time the arithmetic apart
+ *             from the memory traffic)
+ * Enqueued on `stream` (NULL = the null stream); the coefficient tables are
+ * built in a context buffer (allocated or grown on first use).  Errors:
+ * HC_E_INVALID (NULL arguments, negative sizes, repeat < 1, unknown engine),
+ * HC_E_UNSUPPORTED (term-list system, n > 8), HC_E_DEVICE. */
+enum { HC_EVAL_ROWS = 0, HC_EVAL_MFMA = 1 };
+hc_status hc_eval_dense_device(hc_ctx *ctx, const hc_system *sys, const hc_c64 *p_target, int32_t n_inst,
+                               const float *x, int32_t n_pts, int32_t engine, int32_t repeat, float *F,
+                               float *J, void *stream);
+
 /* Duplicate marking of a point set (the merge step of monodromy, which the paper
  * uses to compute its start systems, section 7): keep[i] = 1 unless an earlier
  * point j < i lies within the relative tolerance,

@@ -23,7 +23,7 @@ SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp")
            os.path.join(CSRC, "hc_terms_g20.hip"), os.path.join(CSRC, "hc_lu.hip"),
            os.path.join(CSRC, "hc_peak.hip"), os.path.join(CSRC, "hc_scratch.hip"),
            os.path.join(CSRC, "hc_endgame.hip"), os.path.join(CSRC, "hc_distinct.hip"),
-           os.path.join(CSRC, "hc_wave.hip")]
+           os.path.join(CSRC, "hc_wave.hip"), os.path.join(CSRC, "hc_eval.hip")]
 ARCH = "gfx950"
 
 
@@ -38,8 +38,11 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feat
          "-fPIC"]
 # The 32-row group LU of the standalone solver is larger than the unroller's
 # default budget for #pragma unroll; rolled, its register rows would go to
-# scratch memory.
-EXTRA_FLAGS = {"hc_lu.hip": ["-mllvm", "-pragma-unroll-threshold=65536"]}
+# scratch memory.  The matrix-core evaluation keeps its accumulators in
+# ordinary VGPRs (gfx950 allows either file) rather than in AGPRs, which would
+# cost a copy of every result before the Euler sums read it.
+EXTRA_FLAGS = {"hc_lu.hip": ["-mllvm", "-pragma-unroll-threshold=65536"],
+               "hc_eval.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def build(verbose: bool = False) -> str:

@@ -1042,6 +1042,55 @@ hc_status hc_distinct_device(hc_ctx *c, int32_t n, int64_t count, const hc_c64 *
     return HC_OK;
 }
 
+hc_status hc_eval_dense_device(hc_ctx *c, const hc_system *s, const hc_c64 *p_target, int32_t n_inst,
+                               const float *x, int32_t n_pts, int32_t engine, int32_t repeat, float *F, float *J,
+                               void *stream)
+{
+    clear_error();
+    if (!c || !s) return fail(HC_E_INVALID, "hc_eval_dense_device: NULL context or system");
+    if (n_inst < 0 || n_pts < 0 || repeat < 1 || (engine != HC_EVAL_ROWS && engine != HC_EVAL_MFMA))
+        return fail(HC_E_INVALID, "hc_eval_dense_device: n_inst = %d, n_pts = %d, repeat = %d, engine = %d", n_inst,
+                    n_pts, repeat, engine);
+    if (s->layout != HC_LAYOUT_DENSE || s->n > 8)
+        return fail(HC_E_UNSUPPORTED, "hc_eval_dense_device: needs a dense-table system with n <= 8 (n = %d)", s->n);
+    if ((long long)n_inst * n_pts == 0) return HC_OK;
+    if (!x || !F || !J || (!p_target && s->n_params > 0))
+        return fail(HC_E_INVALID, "hc_eval_dense_device: NULL array");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_slots = s->n * s->T;
+    const size_t b64 = (size_t)n_inst * n_slots * 2 * sizeof(double);
+    HIP_TRY(c->evtab.ensure(b64 + (size_t)n_inst * n_slots * 2 * sizeof(float)));
+    PrepArgs pa;
+    pa.n = s->n;
+    pa.T = s->T;
+    pa.n_inst = n_inst;
+    pa.n_params = s->n_params;
+    pa.n_slots = n_slots;
+    pa.slot_ptr = s->d_slot_ptr;
+    pa.slot_term = s->d_slot_term;
+    pa.slot_mult = s->d_slot_mult;
+    pa.term_const = s->d_term_const;
+    pa.map_ptr = s->d_map_ptr;
+    pa.map_col = s->d_map_col;
+    pa.map_val = s->d_map_val;
+    pa.params = reinterpret_cast<const double *>(p_target);
+    pa.out64 = static_cast<double *>(c->evtab.p);
+    pa.out32 = reinterpret_cast<float *>(static_cast<char *>(c->evtab.p) + b64);
+    HIP_TRY(launch_prep(pa, st));
+    EvalArgs ea;
+    ea.n = s->n;
+    ea.n_inst = n_inst;
+    ea.n_pts = n_pts;
+    ea.repeat = repeat;
+    ea.tab = pa.out32;
+    ea.x = x;
+    ea.F = F;
+    ea.J = J;
+    HIP_TRY(launch_eval(ea, engine, st));
+    return HC_OK;
+}
+
 hc_status hc_measure_vector_peak(hc_ctx *c, int32_t fp64, double *tflops)
 {
     clear_error();

@@ -101,6 +101,7 @@ struct hc_ctx {
     hcx::DevBuf counter; // suspended-path counter, then two stage counters (profiling)
     hcx::DevBuf queue;   // batch: per-pass job descriptors, work items, queue heads
     hcx::DevBuf eg;      // end-game: candidate list, samples and estimates
+    hcx::DevBuf evtab;   // hc_eval_dense_device: the instances' tables (FP64 then FP32)
     std::vector<hcx::TrackArgs> h_jobs;   // host copies kept alive across the async uploads
     std::vector<hcx::QueueItem> h_items;
     std::vector<unsigned char> h_blob;   // batch: staging of the one upload per call

@@ -245,6 +245,18 @@ hipError_t launch_track_wave(int n, const TrackArgs &a, int *list, unsigned *cou
 // Duplicate marking of count points of n complex entries (hc_distinct.hip).
 hipError_t launch_distinct(int n, long long count, const double *pts, double tol, int *keep, hipStream_t st);
 
+// Batched FP32 evaluation of a dense quadratic system (tables as the trackers
+// read them) and its Jacobian at n_pts points of each instance.
+struct EvalArgs {
+    int n, n_inst, n_pts, repeat;
+    const float *tab;         // [n_inst][n][T][2] FP32 kernel tables
+    const float *x;           // [n_inst][n_pts][n][2]
+    float *F;                 // [n_inst][n_pts][n][2]
+    float *J;                 // [n_inst][n_pts][n][n][2]: J[r][a] = dF_r / dx_a
+};
+// engine 0: one Jacobian row per lane (vector ALUs); 1: matrix cores
+hipError_t launch_eval(const EvalArgs &a, int engine, hipStream_t st);
+
 // Measured vector FMA rate (hc_peak.hip), TFLOP/s.
 hipError_t measure_peak_fma(bool fp64, double *tflops, hipStream_t st);
 

@@ -1,15 +1,18 @@
 // hc_peak.hip -- measured vector FMA rate of the device, the denominator check
 // of the trackers' ALU roofline.  Every lane runs independent FMA chains on
-// register values (no memory traffic inside the timed loop).  Built like every
-// other source here with packed FP32 switched off, so the FP32 figure is the
-// rate of plain (one-lane-one-value) FP32 FMAs that the trackers' code runs on.
+// register values (no memory traffic inside the timed loop), all operands in
+// per-lane vector registers: an operand shared by the wavefront would sit in a
+// scalar register, and that form issues markedly slower on gfx950 (65-74
+// against 118-126 TFLOP/s for FP32).  Built like every other source here with
+// packed FP32 switched off, so the FP32 figure is the rate of plain
+// (one-lane-one-value) FP32 FMAs that the trackers' code runs on.
 #include "hc_internal.h"
 
 namespace hcx {
 
 namespace {
 
-constexpr int kChains = 16;        // independent accumulators per lane
+constexpr int kChains = 32;        // independent accumulators per lane
 constexpr int kPeakThreads = 256;  // per block
 
 // acc <- acc * b + c, kChains chains per lane, `iters` rounds.  seed = {b, c,
@@ -19,7 +22,9 @@ template <typename R>
 __global__ __launch_bounds__(kPeakThreads) void k_peak_fma(const R *__restrict__ seed, R *__restrict__ out,
                                                              int iters)
 {
-    const R b = seed[0], c = seed[1];
+    // per-lane operands (vector registers); the perturbation keeps the chains
+    // bounded (|b| < 1) and different in every lane
+    const R b = seed[0] + R(threadIdx.x) * R(1e-9), c = seed[1] + R(threadIdx.x) * R(1e-9);
     R acc[kChains];
 #pragma unroll
     for (int i = 0; i < kChains; i++) acc[i] = seed[2] + R(i) * R(1e-3) + R(threadIdx.x) * R(1e-6);

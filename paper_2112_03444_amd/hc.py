@@ -29,6 +29,7 @@ STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "
 HC_MAX_N = 20
 HC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed workspace of hc_track_device_noalloc, per device
 HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
+HC_EVAL_ROWS, HC_EVAL_MFMA = 0, 1
 
 
 class HcError(RuntimeError):
@@ -142,6 +143,8 @@ def lib():
         L.hc_measure_vector_peak.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double)]
         L.hc_distinct_device.restype = ctypes.c_int
         L.hc_distinct_device.argtypes = [P, I32, I64, P, ctypes.c_double, P, P]
+        L.hc_eval_dense_device.restype = ctypes.c_int
+        L.hc_eval_dense_device.argtypes = [P, P, P, I32, P, I32, I32, I32, P, P, P]
         L.hc_homogenize.restype = ctypes.c_int
         L.hc_homogenize.argtypes = [I32, I32, P, P, P, P, I32, I32, P]
         _lib = L
@@ -453,6 +456,36 @@ class Context:
                                         float(tol), ctypes.c_void_p(keep.data_ptr()),
                                         ctypes.c_void_p(stream.cuda_stream)))
         return keep
+
+    def eval_dense_device(self, sys: "System", p_target, x, engine: int = 0, repeat: int = 1, F=None, J=None,
+                          stream=None):
+        """hc_eval_dense_device: F and its Jacobian in FP32 at the points x
+        (complex64 [n_inst, n_pts, n] on the device) of the instances whose
+        coefficients (parameters) are p_target (complex128 [n_inst, n_params]).
+        engine: HC_EVAL_ROWS (0, vector ALUs) or HC_EVAL_MFMA (1, matrix cores).
+        Returns (F [n_inst, n_pts, n], J [n_inst, n_pts, n, n]), complex64."""
+        import torch
+        if x.dim() != 3 or x.dtype != torch.complex64 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous complex64 tensor [n_inst, n_pts, n]")
+        n_inst, n_pts, n = x.shape
+        if n != sys.n:
+            raise ValueError(f"x has {n} unknowns, the system {sys.n}")
+        p = p_target.contiguous()
+        if p.dtype != torch.complex128 or p.shape[0] != n_inst:
+            raise ValueError("p_target must be complex128 [n_inst, n_params]")
+        if F is None:
+            F = torch.empty((n_inst, n_pts, n), dtype=torch.complex64, device=x.device)
+        if J is None:
+            J = torch.empty((n_inst, n_pts, n, n), dtype=torch.complex64, device=x.device)
+        if F.shape != (n_inst, n_pts, n) or J.shape != (n_inst, n_pts, n, n):
+            raise ValueError("F must be [n_inst, n_pts, n] and J [n_inst, n_pts, n, n]")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().hc_eval_dense_device(self.handle, sys.handle, ctypes.c_void_p(p.data_ptr()), n_inst,
+                                          ctypes.c_void_p(x.data_ptr()), n_pts, int(engine), int(repeat),
+                                          ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(J.data_ptr()),
+                                          ctypes.c_void_p(stream.cuda_stream)))
+        return F, J
 
     def measure_vector_peak(self, fp64: bool) -> float:
         """hc_measure_vector_peak: the device's measured FMA rate in TFLOP/s

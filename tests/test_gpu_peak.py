@@ -1,8 +1,9 @@
 """The measured vector FMA rates (hc_measure_vector_peak) against MI355X's
-published vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s with packed FP32
-(two values per lane and instruction), so 78.6 for the plain FP32 FMAs this
-library is built with.  A rate above the published peak would mean a wrong
-FLOP count; one far below it a broken measurement."""
+published vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s.  The library is
+built without packed FP32 instructions; plain FP32 FMAs with vector-register
+operands still issue well above half the published FP32 peak on gfx950, so the
+FP32 figure is bounded by the published peak itself.  A rate above a published
+peak would mean a wrong FLOP count; one far below it a broken measurement."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -20,5 +21,5 @@ def test_measured_vector_peaks(ctx):
     f32 = ctx.measure_vector_peak(False)
     f64 = ctx.measure_vector_peak(True)
     print(f"measured FMA rates: FP32 plain {f32:.1f}, FP64 {f64:.1f} TFLOP/s")
-    assert 0.3 * 78.6 < f32 <= 1.1 * 157.3
+    assert 0.5 * 157.3 < f32 <= 1.1 * 157.3
     assert 0.3 * 78.6 < f64 <= 1.1 * 78.6
