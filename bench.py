@@ -356,7 +356,7 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4, sample=16):
                        f"{n_start}-solution monodromy start set ({n_inst * n_start:,} paths)",
            "oracle_sample": f"first {sample} instances, {odt:.1f} s"}
     out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
-                               "k_track_terms<0,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
+                               "k_track_terms<3,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
                                f"oracle counters of the first {sample} instances, scaled to {n_inst}",
                                (oep, ost), n_inst, n_start, osamp_eg))
     ctx.free_system(sysh)
@@ -524,7 +524,7 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_fp64=256):
             useful = float(gold["useful_flops_per_instance"]) * ni / 2
             src = f"oracle counters of instances {list(gold['instances'])} (both legs), scaled to {ni}"
         res["roofline"] = roofline(profs, "fp32" if mode == "mixed" else "fp64",
-                                   f"k_track_terms<2,{'float' if mode == 'mixed' else 'double'},true>", w_c,
+                                   f"k_track_terms<4,{'float' if mode == 'mixed' else 'double'},true>", w_c,
                                    w_eval_terms_kernel(S, True) + w_lu(n), useful, src)
         out[mode] = res
         log(f"bench: trifocal {mode} ({ni} instances): {dt * 1e3:.1f} ms/step, {ni * n_start / dt:.3e} tracks/s "

@@ -365,7 +365,7 @@ hc_status hc_solve_batched_device(hc_ctx *ctx, int32_t n, int64_t batch, int32_t
  *             from the memory traffic)
  * Enqueued on `stream` (NULL = the null stream); the coefficient tables are
  * built in a context buffer (allocated or grown on first use).  Errors:
- * HC_E_INVALID (NULL arguments, negative sizes, repeat < 1, unknown engine),
+ * HC_E_INVALID (NULL arguments, negative sizes, n_pts > 2^30, repeat < 1, unknown engine),
  * HC_E_UNSUPPORTED (term-list system, n > 8), HC_E_DEVICE. */
 enum { HC_EVAL_ROWS = 0, HC_EVAL_MFMA = 1 };
 hc_status hc_eval_dense_device(hc_ctx *ctx, const hc_system *sys, const hc_c64 *p_target, int32_t n_inst,

@@ -232,8 +232,8 @@ static hc_status load_system_impl(hc_ctx *c, const hc_system_desc *d, int32_t la
     if (layout == HC_LAYOUT_TERMS && n < 2)
         return fail(HC_E_UNSUPPORTED, "hc_load_system: term lists need n >= 2");
     // term-list kernel kind: the quadratic kernels where they apply
-    const int tk = layout != HC_LAYOUT_TERMS ? 0 : (max_deg <= 2 && n <= 16) ? 0 : n <= 16 ? 1 : 2;
-    const bool gen = layout == HC_LAYOUT_TERMS && tk != 0;
+    const int tk = layout != HC_LAYOUT_TERMS ? 0 : term_kind_for(max_deg, n);
+    const bool gen = layout == HC_LAYOUT_TERMS && term_kind_general(tk);
     if (!d->coef_rowptr && d->n_params != nt)
         return fail(HC_E_INVALID, "hc_load_system: identity coefficient map needs n_params == n_terms (%d != %d)",
                     d->n_params, nt);
@@ -1048,7 +1048,8 @@ hc_status hc_eval_dense_device(hc_ctx *c, const hc_system *s, const hc_c64 *p_ta
 {
     clear_error();
     if (!c || !s) return fail(HC_E_INVALID, "hc_eval_dense_device: NULL context or system");
-    if (n_inst < 0 || n_pts < 0 || repeat < 1 || (engine != HC_EVAL_ROWS && engine != HC_EVAL_MFMA))
+    if (n_inst < 0 || n_pts < 0 || n_pts > (1 << 30) || repeat < 1 ||
+        (engine != HC_EVAL_ROWS && engine != HC_EVAL_MFMA))
         return fail(HC_E_INVALID, "hc_eval_dense_device: n_inst = %d, n_pts = %d, repeat = %d, engine = %d", n_inst,
                     n_pts, repeat, engine);
     if (s->layout != HC_LAYOUT_DENSE || s->n > 8)

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_eval_mfma(EvalArgs a)
 template <int N>
 hipError_t launch_n(const EvalArgs &a, int engine, hipStream_t st)
 {
-    const long long chunks = engine == 0 ? (a.n_pts + 31) / 32 : (a.n_pts + 63) / 64;
+    const long long chunks = engine == 0 ? ((long long)a.n_pts + 31) / 32 : ((long long)a.n_pts + 63) / 64;
     const long long blocks = chunks * a.n_inst;
     if (blocks > 0x7fffffffll) return hipErrorInvalidValue;
     if (engine == 0)

@@ -623,21 +623,26 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 //   * quadratic (kTermsQ16): degree <= 2, n <= 16; the slot's variables are
 //     packed as a | b << 8 in 16 bits (0xFF: no factor, so 0xFFFF is a constant
 //     and an unused slot is 0xFFFF with c_k = 0);
-//   * general degree (kTermsG16: n <= 16; kTermsG20: n <= 20): the monomial's
+//   * quadratic with a 14-row solver (kTermsQ14: degree <= 2, n <= 14), the
+//     same slots as kTermsQ16;
+//   * general degree (kTermsG16: n <= 16; kTermsG18: n <= 18; kTermsG20: n <= 20): the monomial's
 //     factors, with repetition, in the bytes of a 64-bit word, lowest byte first
 //     (0xFF: no factor, so at most 8 factors), plus a per-slot degree that is the
 //     largest over the equations (equations keep their terms in decreasing
 //     degree, so that maximum is tight), on which the kernels branch uniformly.
 // Kernels run with NM rows per group of G lanes: lanes r >= n carry the
-// identity row e_r with a zero right-hand side and never pivot.
-enum TermKind { kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermKinds = 3 };
+// identity row e_r with a zero right-hand side and never pivot (lanes r >= NM,
+// where NM < G, a zero row).  The solver's row count NM bounds every
+// elimination row's length, so a system runs on the kind with the smallest NM
+// that holds it.
+enum TermKind { kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermsQ14 = 3, kTermsG18 = 4, kTermKinds = 5 };
 
 template <int TK>
 struct TermCfg {
-    static constexpr int NM = TK == kTermsG20 ? 20 : 16;  // rows of the group solver
-    static constexpr int G = TK == kTermsG20 ? 32 : 16;   // lanes per path
-    static constexpr bool GEN = TK != kTermsQ16;          // general-degree slots
-    static constexpr int MAXD = GEN ? 8 : 2;               // factors per slot
+    static constexpr int NM = TK == kTermsG20 ? 20 : TK == kTermsG18 ? 18 : TK == kTermsQ14 ? 14 : 16;  // solver rows
+    static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;  // lanes per path
+    static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14;           // general-degree slots
+    static constexpr int MAXD = GEN ? 8 : 2;                                    // factors per slot
 };
 
 constexpr int kTermsN = 16;

@@ -1,9 +1,12 @@
-// hc_terms_q16.hip -- term-list tracker kernels of kind 0 (degree <= 2, n <= 16, 16 lanes per path).
+// hc_terms_q16.hip -- term-list tracker kernels of kind 0 (degree <= 2, n <= 16, 16 lanes per path)
+// and the dispatch over all kinds.
 #include "hc_terms_impl.h"
 
 HC_TERMS_INSTANTIATE(0)
 HC_TERMS_EXTERN(1)  // hc_terms_g16.hip
 HC_TERMS_EXTERN(2)  // hc_terms_g20.hip
+HC_TERMS_EXTERN(3)  // hc_terms_q14.hip
+HC_TERMS_EXTERN(4)  // hc_terms_g18.hip
 
 namespace hcx {
 
@@ -14,6 +17,8 @@ hipError_t launch_track_terms(int tk, bool fp32, const TrackArgs &a, hipStream_t
     case 0: return launch_track_terms_k<0>(fp32, a, st);
     case 1: return launch_track_terms_k<1>(fp32, a, st);
     case 2: return launch_track_terms_k<2>(fp32, a, st);
+    case 3: return launch_track_terms_k<3>(fp32, a, st);
+    case 4: return launch_track_terms_k<4>(fp32, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -25,6 +30,8 @@ hipError_t launch_track_queue_terms(int tk, bool fp32, bool param, const TrackAr
     case 0: return launch_track_queue_terms_k<0>(fp32, param, jobs, items, n_items, head, n_waves, st);
     case 1: return launch_track_queue_terms_k<1>(fp32, param, jobs, items, n_items, head, n_waves, st);
     case 2: return launch_track_queue_terms_k<2>(fp32, param, jobs, items, n_items, head, n_waves, st);
+    case 3: return launch_track_queue_terms_k<3>(fp32, param, jobs, items, n_items, head, n_waves, st);
+    case 4: return launch_track_queue_terms_k<4>(fp32, param, jobs, items, n_items, head, n_waves, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -35,6 +42,8 @@ int queue_waves_terms(int tk, bool fp32, bool param)
     case 0: return queue_waves_terms_k<0>(fp32, param);
     case 1: return queue_waves_terms_k<1>(fp32, param);
     case 2: return queue_waves_terms_k<2>(fp32, param);
+    case 3: return queue_waves_terms_k<3>(fp32, param);
+    case 4: return queue_waves_terms_k<4>(fp32, param);
     default: return 0;
     }
 }
@@ -45,6 +54,8 @@ hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st)
     case 0: return launch_refine_terms_k<0>(&a, 1, a.total, false, st);
     case 1: return launch_refine_terms_k<1>(&a, 1, a.total, false, st);
     case 2: return launch_refine_terms_k<2>(&a, 1, a.total, false, st);
+    case 3: return launch_refine_terms_k<3>(&a, 1, a.total, false, st);
+    case 4: return launch_refine_terms_k<4>(&a, 1, a.total, false, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -55,6 +66,8 @@ hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long
     case 0: return launch_refine_terms_k<0>(a, count, max_total, true, st);
     case 1: return launch_refine_terms_k<1>(a, count, max_total, true, st);
     case 2: return launch_refine_terms_k<2>(a, count, max_total, true, st);
+    case 3: return launch_refine_terms_k<3>(a, count, max_total, true, st);
+    case 4: return launch_refine_terms_k<4>(a, count, max_total, true, st);
     default: return hipErrorInvalidValue;
     }
 }

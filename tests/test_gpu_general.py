@@ -61,7 +61,8 @@ def linear_rows(n, count):
     return [(1, list(range(n)))] * count
 
 
-# (n, spec): kind 1 (any degree, n <= 16) and kind 2 (n 17..20)
+# (n, spec): kinds 1 (any degree, n <= 16), 4 (n 17..18) and 2 (n 19..20), and the
+# quadratic kind 0 (n 15..16)
 SPECS = {
     "cubic3": (3, [(3, [0, 1, 2])] * 3),
     "deg54": (2, [(5, [0, 1]), (4, [0, 1])]),
@@ -71,6 +72,7 @@ SPECS = {
     "deg5_n18": (18, [(5, [0, 1]), (3, [0, 1, 2])] + linear_rows(18, 16)),
     "cubic_n20": (20, [(3, [0, 1, 2]), (2, [0, 1, 2, 3])] + linear_rows(20, 18)),
     "quad_n17": (17, [(2, [0, 1, 2]), (2, [0, 1, 2])] + linear_rows(17, 15)),
+    "quad_n15": (15, [(2, [0, 1, 2, 3]), (2, [0, 1, 2])] + linear_rows(15, 13)),
 }
 
 
