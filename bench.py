@@ -91,6 +91,16 @@ def w_term(d: int, blend: int) -> int:
     return blend + 6 * (3 * d - 5) + 8 + 8 * d
 
 
+def term_kind(system) -> int:
+    """The library's term-list kernel kind for a system (the smallest solver that
+    holds it): 5, 3, 0 for degree <= 2 and n <= 10, 14, 16; 1, 4, 2 for higher
+    degree and n <= 16, 18, 20."""
+    n, d = int(system.n), int(np.asarray(system.term_exp).sum(axis=1).max())
+    if d <= 2:
+        return 5 if n <= 10 else 3 if n <= 14 else 0 if n <= 16 else 4 if n <= 18 else 2
+    return 1 if n <= 16 else 4 if n <= 18 else 2
+
+
 def w_eval_terms_kernel(system, param: bool) -> int:
     """Kernel FLOPs of one evaluation of [H_x | rhs] from term lists: per term
     w_term (parameter homotopy: 8 for the blend and c1 - c0), plus 37 per
@@ -356,7 +366,8 @@ def vision_leg(ctx, hc, torch, steps, warmup, n_views=4, sample=16):
                        f"{n_start}-solution monodromy start set ({n_inst * n_start:,} paths)",
            "oracle_sample": f"first {sample} instances, {odt:.1f} s"}
     out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
-                               "k_track_terms<3,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
+                               "k_track_terms<" + str(term_kind(S)) + ",{},true>", w_c,
+                               w_eval_terms_kernel(S, True) + w_lu(n), useful,
                                f"oracle counters of the first {sample} instances, scaled to {n_inst}",
                                (oep, ost), n_inst, n_start, osamp_eg))
     ctx.free_system(sysh)
@@ -426,7 +437,8 @@ def fivept_leg(ctx, hc, torch, steps, warmup, sample=32):
                        f"{S.n_terms} terms of degree <= 3), parameter homotopy from a {n_start}-solution "
                        f"monodromy start set ({n_inst * n_start:,} paths); oracle on the first {sample}"}
     out.update(run_param_modes(ctx, hc, torch, sysh, p, ps, start, ep, st, info, steps, warmup, S,
-                               "k_track_terms<1,{},true>", w_c, w_eval_terms_kernel(S, True) + w_lu(n), useful,
+                               "k_track_terms<" + str(term_kind(S)) + ",{},true>", w_c,
+                               w_eval_terms_kernel(S, True) + w_lu(n), useful,
                                f"oracle counters of the first {sample} instances, scaled", (oep, ost), n_inst,
                                n_start))
     ctx.free_system(sysh)
@@ -524,7 +536,7 @@ def trifocal_leg(ctx, hc, torch, steps, warmup, n_inst=1024, n_inst_fp64=256):
             useful = float(gold["useful_flops_per_instance"]) * ni / 2
             src = f"oracle counters of instances {list(gold['instances'])} (both legs), scaled to {ni}"
         res["roofline"] = roofline(profs, "fp32" if mode == "mixed" else "fp64",
-                                   f"k_track_terms<4,{'float' if mode == 'mixed' else 'double'},true>", w_c,
+                                   f"k_track_terms<{term_kind(S)},{'float' if mode == 'mixed' else 'double'},true>", w_c,
                                    w_eval_terms_kernel(S, True) + w_lu(n), useful, src)
         out[mode] = res
         log(f"bench: trifocal {mode} ({ni} instances): {dt * 1e3:.1f} ms/step, {ni * n_start / dt:.3e} tracks/s "

@@ -21,7 +21,8 @@ SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp")
            os.path.join(CSRC, "hc_kernels.hip"), os.path.join(CSRC, "hc_track_group.hip"),
            os.path.join(CSRC, "hc_terms_q16.hip"), os.path.join(CSRC, "hc_terms_g16.hip"),
            os.path.join(CSRC, "hc_terms_g20.hip"), os.path.join(CSRC, "hc_terms_q14.hip"),
-           os.path.join(CSRC, "hc_terms_g18.hip"), os.path.join(CSRC, "hc_lu.hip"),
+           os.path.join(CSRC, "hc_terms_g18.hip"), os.path.join(CSRC, "hc_terms_q10.hip"),
+           os.path.join(CSRC, "hc_lu.hip"),
            os.path.join(CSRC, "hc_peak.hip"), os.path.join(CSRC, "hc_scratch.hip"),
            os.path.join(CSRC, "hc_endgame.hip"), os.path.join(CSRC, "hc_distinct.hip"),
            os.path.join(CSRC, "hc_wave.hip"), os.path.join(CSRC, "hc_eval.hip")]

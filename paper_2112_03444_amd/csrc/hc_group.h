@@ -623,8 +623,8 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 //   * quadratic (kTermsQ16): degree <= 2, n <= 16; the slot's variables are
 //     packed as a | b << 8 in 16 bits (0xFF: no factor, so 0xFFFF is a constant
 //     and an unused slot is 0xFFFF with c_k = 0);
-//   * quadratic with a 14-row solver (kTermsQ14: degree <= 2, n <= 14), the
-//     same slots as kTermsQ16;
+//   * quadratic with a 10- or 14-row solver (kTermsQ10: degree <= 2, n <= 10;
+//     kTermsQ14: n <= 14), the same slots as kTermsQ16;
 //   * general degree (kTermsG16: n <= 16; kTermsG18: n <= 18; kTermsG20: n <= 20): the monomial's
 //     factors, with repetition, in the bytes of a 64-bit word, lowest byte first
 //     (0xFF: no factor, so at most 8 factors), plus a per-slot degree that is the
@@ -635,13 +635,23 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 // where NM < G, a zero row).  The solver's row count NM bounds every
 // elimination row's length, so a system runs on the kind with the smallest NM
 // that holds it.
-enum TermKind { kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermsQ14 = 3, kTermsG18 = 4, kTermKinds = 5 };
+enum TermKind {
+    kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermsQ14 = 3, kTermsG18 = 4, kTermsQ10 = 5, kTermKinds = 6
+};
 
 template <int TK>
 struct TermCfg {
-    static constexpr int NM = TK == kTermsG20 ? 20 : TK == kTermsG18 ? 18 : TK == kTermsQ14 ? 14 : 16;  // solver rows
-    static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;  // lanes per path
-    static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14;           // general-degree slots
+    static constexpr int NM = TK == kTermsG20   ? 20  // rows of the group solver
+                              : TK == kTermsG18 ? 18
+                              : TK == kTermsQ14 ? 14
+                              : TK == kTermsQ10 ? 10
+                                                : 16;
+    static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;          // lanes per path
+    static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14 && TK != kTermsQ10;  // general-degree slots
+    // wavefronts per SIMD the tracker is compiled for: the short rows of q10 fit
+    // 3 (168 VGPRs, a few spills), which measured 14-19% faster than 2 on the
+    // 3-view batch; the others need more than 168 registers
+    static constexpr int WAVES = TK == kTermsQ10 ? 3 : 2;
     static constexpr int MAXD = GEN ? 8 : 2;                                    // factors per slot
 };
 

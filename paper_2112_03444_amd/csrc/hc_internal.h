@@ -217,17 +217,18 @@ int group_lanes(int n);
 // max_total = the largest path count of the jobs.
 hipError_t launch_refine_group(int n, const RefineArgs *a, int count, long long max_total, bool many, hipStream_t st);
 
-// Term-list layout (hc_terms_impl.h): kind tk = 3 (degree <= 2, n <= 14),
-// 0 (degree <= 2, n <= 16), 1 (any degree <= 8, n <= 16), 4 (any degree <= 8,
-// n <= 18) or 2 (any degree <= 8, n <= 20); 16 lanes per path for kinds 0, 1
-// and 3, 32 for kinds 2 and 4.
-constexpr int kTermKindCount = 5;
+// Term-list layout (hc_terms_impl.h): kind tk = 5, 3 or 0 (degree <= 2,
+// n <= 10, 14 or 16), 1 (any degree <= 8, n <= 16), 4 (any degree <= 8,
+// n <= 18) or 2 (any degree <= 8, n <= 20); 16 lanes per path for kinds 0, 1, 3
+// and 5, 32 for kinds 2 and 4.
+constexpr int kTermKindCount = 6;
 constexpr int term_kind_lanes(int tk) { return tk == 2 || tk == 4 ? 32 : 16; }
 constexpr bool term_kind_general(int tk) { return tk == 1 || tk == 2 || tk == 4; }
 // The kind with the smallest solver that holds a term-list system.
 constexpr int term_kind_for(int max_deg, int n)
 {
-    return max_deg <= 2 ? (n <= 14 ? 3 : n <= 16 ? 0 : n <= 18 ? 4 : 2) : (n <= 16 ? 1 : n <= 18 ? 4 : 2);
+    return max_deg <= 2 ? (n <= 10 ? 5 : n <= 14 ? 3 : n <= 16 ? 0 : n <= 18 ? 4 : 2)
+                        : (n <= 16 ? 1 : n <= 18 ? 4 : 2);
 }
 hipError_t launch_track_terms(int tk, bool fp32, const TrackArgs &a, hipStream_t st);
 hipError_t launch_track_queue_terms(int tk, bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,

@@ -27,7 +27,7 @@ constexpr size_t terms_wave_bytes()
 
 // Persistent tracker for one job on the term-list layout.
 template <int TK, typename R, bool PARAM>
-__global__ __launch_bounds__(256, 2) void k_track_terms(const TrackArgs a)
+__global__ __launch_bounds__(256, TermCfg<TK>::WAVES) void k_track_terms(const TrackArgs a)
 {
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ __align__(16) unsigned char buf[terms_lds_bytes<TK>()];
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256, 2) void k_track_terms(const TrackArgs a)
 
 // Persistent tracker over a device work queue of term-list jobs of one kind.
 template <int TK, typename R, bool PARAM>
-__global__ __launch_bounds__(256, 2) void k_track_queue_terms(const TrackArgs *__restrict__ jobs,
+__global__ __launch_bounds__(256, TermCfg<TK>::WAVES) void k_track_queue_terms(const TrackArgs *__restrict__ jobs,
                                                               const QueueItem *__restrict__ items, int n_items,
                                                               unsigned *head)
 {
