@@ -648,10 +648,12 @@ struct TermCfg {
                                                 : 16;
     static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;          // lanes per path
     static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14 && TK != kTermsQ10;  // general-degree slots
-    // wavefronts per SIMD the tracker is compiled for: the short rows of q10 fit
-    // 3 (168 VGPRs, a few spills), which measured 14-19% faster than 2 on the
-    // 3-view batch; the others need more than 168 registers
-    static constexpr int WAVES = TK == kTermsQ10 ? 3 : 2;
+    // wavefronts per SIMD the tracker is compiled for: 3 where the LDS slices
+    // allow it and the spills at 168 VGPRs cost less than the latency a third
+    // wavefront hides (q10: 14-19% faster on the 3-view batch; g18: 6-8% on the
+    // trifocal batch); q14, q16, g16 and g20 hold more than 160 KB of LDS per CU
+    // at 3 blocks
+    static constexpr int WAVES = (TK == kTermsQ10 || TK == kTermsG18) ? 3 : 2;
     static constexpr int MAXD = GEN ? 8 : 2;                                    // factors per slot
 };
 
