@@ -134,7 +134,8 @@ def time_batch(ctx, sysh, p, g, ep, st, info, opts, steps, warmup, torch):
 def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, useful_source=None):
     """Roofline of the dominant kernel of one mode: the tracking launch (in mixed
     precision one launch of the FP32 tracker whose escalated paths run their
-    FP64 stages inside it).  achieved = useful FLOPs per launch / the launch's
+    FP64 stages inside it, or, on the term-list kinds that escalate in a second
+    launch, the FP32 launch plus that FP64 launch).  achieved = useful FLOPs per launch / the launch's
     mean duration from HIP events on its stream.  Useful FLOPs are the FP64
     oracle's tracking work on this workload (useful_per_step, the same figure for
     both precisions; `useful_source` says how it was counted), else the stages
@@ -144,7 +145,11 @@ def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, us
     ms = float(np.mean([p[f"ms_track_{key}"] for p in profs]))
     launches = max(float(np.mean([p[f"launches_{key}"] for p in profs])), 1.0)
     stages = float(np.mean([p[f"stages_{key}"] + (p["stages_fp64"] if key == "fp32" else 0.0) for p in profs]))
-    per_launch_s = ms / launches * 1e-3
+    # mixed precision with escalation in a second launch (term-list kinds): the
+    # FP64 launch's time belongs to the same tracking work (its stages are
+    # counted above); with inline escalation that interval is empty
+    ms64 = float(np.mean([p["ms_track_fp64"] for p in profs])) if key == "fp32" else 0.0
+    per_launch_s = (ms + ms64) / launches * 1e-3
     if useful_per_step is not None:
         flops, src = float(useful_per_step), useful_source or "oracle"
     else:
@@ -157,6 +162,7 @@ def roofline(profs, kind, kernel, w_contract, w_kernel, useful_per_step=None, us
            "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel version, profiles/ (not live)"
            if traffic is not None else None,
            "kernel": kernel, "kernel_ms_per_launch": round(ms / launches, 4), "launches_per_step": launches,
+           "fp64_pass_ms_per_step": round(ms64, 4),
            "flops_source": src, "flops_per_stage": w_contract, "useful_flops_per_launch": flops / launches,
            "gpu_stages_per_launch": stages / launches, "flops_per_stage_kernel": w_kernel,
            "achieved_kernel_count": round(stages * w_kernel / launches / per_launch_s / 1e12, 3)}

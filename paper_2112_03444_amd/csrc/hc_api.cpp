@@ -514,6 +514,14 @@ static bool wave_fits(const hc_system *s)
     return s->layout == HC_LAYOUT_DENSE && s->kind == HC_TOTAL_DEGREE && s->n >= 2 && s->n <= 8;
 }
 
+// Mixed precision on the single-call group trackers: failed FP32 paths go on in
+// FP64 inside the FP32 launch (dense tables, g16), or in a second, FP64 launch
+// (the other term-list kinds).  The batch tracker always escalates inline.
+static bool inline_escalation(const hc_system *s)
+{
+    return kInlineEsc && (s->layout != HC_LAYOUT_TERMS || term_kind_inline_esc(s->tk));
+}
+
 static int choose_lanes_per_path(const hc_opts &o, const hc_system *s)
 {
     if (o.lanes_per_path == 64) return wave_fits(s) && o.precision == HC_FP64 ? 64 : -1;
@@ -936,7 +944,7 @@ static hc_status track_device_impl(hc_ctx *c, const hc_system *s, const hc_c64 *
         }
         return HC_OK;
     };
-    if (lanes > 1 && mixed && kInlineEsc) {
+    if (lanes > 1 && mixed && inline_escalation(s)) {
         // group tracker: one launch; failed paths and the end zone go on in FP64
         // inside the kernel
         rc = run_pass(true, 1.0, 0, false);
@@ -1684,6 +1692,7 @@ static hc_status track_batch_impl(hc_ctx *c, int32_t n_jobs, const hc_job *jobs,
     };
     rc = run_pass(mixed);
     if (rc != HC_OK) return rc;
+    // the batch tracker escalates inline on every kind (k_track_queue_terms)
     if (mixed && !kInlineEsc) {
         rc = run_pass(false);
         if (rc != HC_OK) return rc;

@@ -648,12 +648,23 @@ struct TermCfg {
                                                 : 16;
     static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;          // lanes per path
     static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14 && TK != kTermsQ10;  // general-degree slots
+    // mixed precision: FP64 stages inside the FP32 launch, else a second launch
+    static constexpr bool INLINE_ESC = term_kind_inline_esc(TK);
     // wavefronts per SIMD the tracker is compiled for: 3 where the LDS slices
     // allow it and the spills at 168 VGPRs cost less than the latency a third
-    // wavefront hides (q10: 14-19% faster on the 3-view batch; g18: 6-8% on the
-    // trifocal batch); q14, q16, g16 and g20 hold more than 160 KB of LDS per CU
-    // at 3 blocks
-    static constexpr int WAVES = (TK == kTermsQ10 || TK == kTermsG18) ? 3 : 2;
+    // wavefront hides -- every FP32 kernel without the inline FP64 stage; the
+    // FP64 kernels of q10 and g18 (14-19% faster on the 3-view batch, 6-8% on
+    // the trifocal batch); q14, q16, g16 and g20 hold more than 160 KB of FP64
+    // LDS slices per CU at 3 blocks
+    template <typename R>
+    static constexpr int waves()
+    {
+        return (sizeof(R) == 4 && !INLINE_ESC) || TK == kTermsQ10 || TK == kTermsG18 ? 3 : 2;
+    }
+    // the batch tracker (a device queue of jobs) escalates inline on every kind:
+    // its small, latency-bound batches lose more to a second launch than they
+    // gain from a third wavefront (serving mix: p50 34 -> 44 ms with two)
+    static constexpr int QUEUE_WAVES = TK == kTermsQ10 || TK == kTermsG18 ? 3 : 2;
     static constexpr int MAXD = GEN ? 8 : 2;                                    // factors per slot
 };
 
@@ -937,7 +948,7 @@ __device__ __attribute__((noinline)) StageOut stage64_terms(const void *vars, co
 // accepted point, h reset to h0 after a failure) -- the wavefront runs the FP64
 // stage, with tables read from global memory, only while one of its groups
 // needs it.
-template <int N, int G, typename R, bool PARAM, typename Src, int TK = -1>
+template <int N, int G, typename R, bool PARAM, typename Src, int TK = -1, int ESC = -1>
 __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *lds)
 {
     constexpr bool TERMS = TK >= 0;
@@ -945,6 +956,10 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     static_assert(G == 4 || G == 8 || G == 16 || G == 32, "group size");
     static_assert(N <= G, "one row per lane");
     static_assert(!TERMS || (N == TermCfg<TKc>::NM && G == TermCfg<TKc>::G), "term-list kind");
+    // FP64 stages inside this (FP32) loop: the dense tables and the term-list
+    // kinds compiled for it, or as the caller asks (ESC >= 0); else failures
+    // stay RUNNING for an FP64 launch
+    constexpr bool kInl = kInlineEsc && (ESC >= 0 ? ESC != 0 : (!TERMS || TermCfg<TKc>::INLINE_ESC));
     constexpr bool R64 = sizeof(R) == 8;
     // dense layout: n = N and T = C(N+2, 2) slots per equation; term lists: runtime
     const int nn = TERMS ? a.n : N;
@@ -1039,7 +1054,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
             escal = steps + rejects + 1;
             h = a.h0;
             succ = 0;
-            if (!kInlineEsc) {
+            if (!kInl) {
                 save(kRunning);
                 return;
             }
@@ -1078,7 +1093,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 const long long gg = (long long)cur_inst * a.n_start + cand;
                 // still going and not yet at this launch's end time
                 if (S.status[gg] == kRunning && S.t[gg] < a.t_final &&
-                    (R64 || kInlineEsc || S.escal[gg] == 0)) {
+                    (R64 || kInl || S.escal[gg] == 0)) {
                     trk = cand;
                     g = gg;
                     gslot = cur_slot;
@@ -1102,7 +1117,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     rejects = S.rejects[g];
                     nits = S.nits[g];
                     escal = S.escal[g];
-                    p64 = R64 || (kInlineEsc && (escal != 0 || t >= a.t_switch));
+                    p64 = R64 || (kInl && (escal != 0 || t >= a.t_switch));
                     lsteps = 0;
                     if (steps_used(steps, rejects, escal) >= a.max_steps)
                         fail(HC_T_MAX_STEPS);
@@ -1136,7 +1151,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 sing = stage_solve<N, G, R, PARAM>(LdsRow<N, R>{cl}, p0, p1, r, base, d2, gam, gam64, xe, te, pred,
                                                    ir, d, nd2);
         }
-        if constexpr (!R64 && kInlineEsc) {
+        if constexpr (!R64 && kInl) {
             if (ballot(act && p64) != 0ull) {
                 const double *q0 = row0_64, *q1 = row1_64;
                 asm volatile("" : "+v"(q0), "+v"(q1));

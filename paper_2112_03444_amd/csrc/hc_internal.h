@@ -224,6 +224,15 @@ hipError_t launch_refine_group(int n, const RefineArgs *a, int count, long long 
 constexpr int kTermKindCount = 6;
 constexpr int term_kind_lanes(int tk) { return tk == 2 || tk == 4 ? 32 : 16; }
 constexpr bool term_kind_general(int tk) { return tk == 1 || tk == 2 || tk == 4; }
+// Mixed precision on a term-list kind: escalation inside the FP32 launch (as on
+// the dense tables) or in a second, FP64 launch.  Without the FP64 stage in its
+// loop every term-list FP32 kernel fits 3 wavefronts per SIMD (168 VGPRs, 0-9
+// spilled, FP32-sized LDS slices) instead of 2, which outweighs the second
+// launch (4-view batch: 754 -> 559 ms per step; 3-view 104 -> 96 ms; trifocal
+// -3.5%).  g16 keeps it inline: the 5-point batch is small for the device and
+// lost 7% with a second launch.  Single-call tracking only: the batch tracker
+// escalates inline on every kind.
+constexpr bool term_kind_inline_esc(int tk) { return tk == 1; }
 // The kind with the smallest solver that holds a term-list system.
 constexpr int term_kind_for(int max_deg, int n)
 {

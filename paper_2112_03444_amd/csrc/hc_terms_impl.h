@@ -23,24 +23,36 @@ constexpr size_t terms_wave_bytes()
     return (size_t)terms_lds_cx<TermCfg<TK>::NM, TermCfg<TK>::G>() * sizeof(cx<double>);
 }
 
+// LDS slice of one wavefront of the tracker in precision R: FP64-sized where
+// FP64 stages run in it (the FP64 tracker, an FP32 tracker with inline
+// escalation), else FP32 entries plus the 64 FP64 stage-point entries of the
+// fp64_residual option.
+template <int TK, typename R>
+constexpr size_t track_wave_bytes()
+{
+    return (sizeof(R) == 8 || TermCfg<TK>::INLINE_ESC)
+               ? terms_wave_bytes<TK>()
+               : (size_t)terms_lds_cx<TermCfg<TK>::NM, TermCfg<TK>::G>() * sizeof(cx<float>) + 64 * sizeof(cx<double>);
+}
+
 }  // namespace
 
 // Persistent tracker for one job on the term-list layout.
 template <int TK, typename R, bool PARAM>
-__global__ __launch_bounds__(256, TermCfg<TK>::WAVES) void k_track_terms(const TrackArgs a)
+__global__ __launch_bounds__(256, TermCfg<TK>::template waves<R>()) void k_track_terms(const TrackArgs a)
 {
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    __shared__ __align__(16) unsigned char buf[terms_lds_bytes<TK>()];
+    __shared__ __align__(16) unsigned char buf[4 * track_wave_bytes<TK, R>()];
     GridSource src{a.head, a.n_items, a.items_per_inst, a.tracks_per_item, a.n_start, false};
     run_items<TermCfg<TK>::NM, TermCfg<TK>::G, R, PARAM, GridSource, TK>(
-        a, src, reinterpret_cast<cx<R> *>(buf + (size_t)wib * terms_wave_bytes<TK>()));
+        a, src, reinterpret_cast<cx<R> *>(buf + (size_t)wib * track_wave_bytes<TK, R>()));
 }
 
 // Persistent tracker over a device work queue of term-list jobs of one kind.
+// Mixed precision escalates inline here on every kind (FP64-sized LDS slices).
 template <int TK, typename R, bool PARAM>
-__global__ __launch_bounds__(256, TermCfg<TK>::WAVES) void k_track_queue_terms(const TrackArgs *__restrict__ jobs,
-                                                              const QueueItem *__restrict__ items, int n_items,
-                                                              unsigned *head)
+__global__ __launch_bounds__(256, TermCfg<TK>::QUEUE_WAVES) void k_track_queue_terms(
+    const TrackArgs *__restrict__ jobs, const QueueItem *__restrict__ items, int n_items, unsigned *head)
 {
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -64,7 +76,7 @@ __global__ __launch_bounds__(256, TermCfg<TK>::WAVES) void k_track_queue_terms(c
         src.first = it;
         src.has_first = true;
         src.done = false;
-        run_items<TermCfg<TK>::NM, TermCfg<TK>::G, R, PARAM, QueueSource, TK>(a, src, lds);
+        run_items<TermCfg<TK>::NM, TermCfg<TK>::G, R, PARAM, QueueSource, TK, 1>(a, src, lds);
         if (src.done && !src.has_pending) break;
     }
 }
