@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define HC_MAX_N 20 /* largest number of unknowns the GPU path handles */
+#define HC_MAX_N 32 /* largest number of unknowns the GPU path handles */
 /* Size of the fixed device workspace of hc_track_device_noalloc (per device). */
 #define HC_NOALLOC_SCRATCH_BYTES (64u << 20)
 
@@ -234,7 +234,8 @@ typedef enum {
                              (c, L, Q per equation); n <= 8                       */
     HC_LAYOUT_TERMS = 2   /* per equation the list of its own terms (section 6's
                              term tables): c x_a x_b for degree <= 2 and n <= 16,
-                             else up to 8 factors per term; n <= HC_MAX_N       */
+                             else up to 8 factors per term; n <= HC_MAX_N (the
+                             paper's largest Jacobian, 32 x 32, section 1)       */
 } hc_layout;
 
 /* hc_load_system with an explicit table layout (hc_load_system uses

@@ -22,6 +22,7 @@ SOURCES = [os.path.join(CSRC, "hc_api.cpp"), os.path.join(CSRC, "hc_server.cpp")
            os.path.join(CSRC, "hc_terms_q16.hip"), os.path.join(CSRC, "hc_terms_g16.hip"),
            os.path.join(CSRC, "hc_terms_g20.hip"), os.path.join(CSRC, "hc_terms_q14.hip"),
            os.path.join(CSRC, "hc_terms_g18.hip"), os.path.join(CSRC, "hc_terms_q10.hip"),
+           os.path.join(CSRC, "hc_terms_g32.hip"),
            os.path.join(CSRC, "hc_lu.hip"),
            os.path.join(CSRC, "hc_peak.hip"), os.path.join(CSRC, "hc_scratch.hip"),
            os.path.join(CSRC, "hc_endgame.hip"), os.path.join(CSRC, "hc_distinct.hip"),
@@ -38,12 +39,13 @@ def hipcc() -> str:
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fPIC"]
-# The 32-row group LU of the standalone solver is larger than the unroller's
-# default budget for #pragma unroll; rolled, its register rows would go to
-# scratch memory.  The matrix-core evaluation keeps its accumulators in
+# The 32-row group LUs of the standalone solver and of the 32-row term-list
+# tracker are larger than the unroller's default budget for #pragma unroll;
+# rolled, their register rows would go to scratch memory.  The matrix-core evaluation keeps its accumulators in
 # ordinary VGPRs (gfx950 allows either file) rather than in AGPRs, which would
 # cost a copy of every result before the Euler sums read it.
 EXTRA_FLAGS = {"hc_lu.hip": ["-mllvm", "-pragma-unroll-threshold=65536"],
+               "hc_terms_g32.hip": ["-mllvm", "-pragma-unroll-threshold=65536"],
                "hc_eval.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 

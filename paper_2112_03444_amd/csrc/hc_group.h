@@ -625,7 +625,8 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 //     and an unused slot is 0xFFFF with c_k = 0);
 //   * quadratic with a 10- or 14-row solver (kTermsQ10: degree <= 2, n <= 10;
 //     kTermsQ14: n <= 14), the same slots as kTermsQ16;
-//   * general degree (kTermsG16: n <= 16; kTermsG18: n <= 18; kTermsG20: n <= 20): the monomial's
+//   * general degree (kTermsG16: n <= 16; kTermsG18: n <= 18; kTermsG20: n <= 20; kTermsG32:
+//     n <= 32, every system above 20 unknowns whatever its degree): the monomial's
 //     factors, with repetition, in the bytes of a 64-bit word, lowest byte first
 //     (0xFF: no factor, so at most 8 factors), plus a per-slot degree that is the
 //     largest over the equations (equations keep their terms in decreasing
@@ -636,17 +637,19 @@ __device__ __attribute__((noinline)) StageOut stage64_dense(const double *q0, co
 // elimination row's length, so a system runs on the kind with the smallest NM
 // that holds it.
 enum TermKind {
-    kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermsQ14 = 3, kTermsG18 = 4, kTermsQ10 = 5, kTermKinds = 6
+    kTermsQ16 = 0, kTermsG16 = 1, kTermsG20 = 2, kTermsQ14 = 3, kTermsG18 = 4, kTermsQ10 = 5, kTermsG32 = 6,
+    kTermKinds = 7
 };
 
 template <int TK>
 struct TermCfg {
-    static constexpr int NM = TK == kTermsG20   ? 20  // rows of the group solver
+    static constexpr int NM = TK == kTermsG32   ? 32  // rows of the group solver
+                              : TK == kTermsG20 ? 20
                               : TK == kTermsG18 ? 18
                               : TK == kTermsQ14 ? 14
                               : TK == kTermsQ10 ? 10
                                                 : 16;
-    static constexpr int G = (TK == kTermsG20 || TK == kTermsG18) ? 32 : 16;          // lanes per path
+    static constexpr int G = (TK == kTermsG20 || TK == kTermsG18 || TK == kTermsG32) ? 32 : 16;  // lanes per path
     static constexpr bool GEN = TK != kTermsQ16 && TK != kTermsQ14 && TK != kTermsQ10;  // general-degree slots
     // mixed precision: FP64 stages inside the FP32 launch, else a second launch
     static constexpr bool INLINE_ESC = term_kind_inline_esc(TK);
@@ -655,16 +658,19 @@ struct TermCfg {
     // wavefront hides -- every FP32 kernel without the inline FP64 stage; the
     // FP64 kernels of q10 and g18 (14-19% faster on the 3-view batch, 6-8% on
     // the trifocal batch); q14, q16, g16 and g20 hold more than 160 KB of FP64
-    // LDS slices per CU at 3 blocks
+    // LDS slices per CU at 3 blocks.  g32's FP64 slices take 136 KB per block
+    // of 4 wavefronts, so one block per CU (its 33-entry FP64 rows get the
+    // whole register file of the SIMD); its FP32 slices allow two.
     template <typename R>
     static constexpr int waves()
     {
+        if (TK == kTermsG32) return sizeof(R) == 4 ? 2 : 1;
         return (sizeof(R) == 4 && !INLINE_ESC) || TK == kTermsQ10 || TK == kTermsG18 ? 3 : 2;
     }
     // the batch tracker (a device queue of jobs) escalates inline on every kind:
     // its small, latency-bound batches lose more to a second launch than they
     // gain from a third wavefront (serving mix: p50 34 -> 44 ms with two)
-    static constexpr int QUEUE_WAVES = TK == kTermsQ10 || TK == kTermsG18 ? 3 : 2;
+    static constexpr int QUEUE_WAVES = TK == kTermsG32 ? 1 : TK == kTermsQ10 || TK == kTermsG18 ? 3 : 2;
     static constexpr int MAXD = GEN ? 8 : 2;                                    // factors per slot
 };
 

@@ -75,7 +75,7 @@ struct hc_system {
     double *d_map_val = nullptr;
     void *d_vars = nullptr;   // term lists: variables of every slot (16- or 64-bit entries)
     int tk = 0;               // term lists: kernel kind (term_kind_for: 5 / 3 / 0: degree <= 2,
-                              //   n <= 10 / 14 / 16; 1 / 4 / 2: any degree, n <= 16 / 18 / 20)
+                              //   n <= 10 / 14 / 16; 1 / 4 / 2 / 6: any degree, n <= 16 / 18 / 20 / 32)
     int max_deg = 0;          // largest term degree
     int *d_sdeg = nullptr;    // general-degree kinds: [T] largest degree of each slot
     int *d_eqdeg = nullptr;   // general-degree kinds: [n] equation degrees

@@ -219,11 +219,11 @@ hipError_t launch_refine_group(int n, const RefineArgs *a, int count, long long 
 
 // Term-list layout (hc_terms_impl.h): kind tk = 5, 3 or 0 (degree <= 2,
 // n <= 10, 14 or 16), 1 (any degree <= 8, n <= 16), 4 (any degree <= 8,
-// n <= 18) or 2 (any degree <= 8, n <= 20); 16 lanes per path for kinds 0, 1, 3
-// and 5, 32 for kinds 2 and 4.
-constexpr int kTermKindCount = 6;
-constexpr int term_kind_lanes(int tk) { return tk == 2 || tk == 4 ? 32 : 16; }
-constexpr bool term_kind_general(int tk) { return tk == 1 || tk == 2 || tk == 4; }
+// n <= 18), 2 (any degree <= 8, n <= 20) or 6 (any degree <= 8, n <= 32); 16
+// lanes per path for kinds 0, 1, 3 and 5, 32 for kinds 2, 4 and 6.
+constexpr int kTermKindCount = 7;
+constexpr int term_kind_lanes(int tk) { return tk == 2 || tk == 4 || tk == 6 ? 32 : 16; }
+constexpr bool term_kind_general(int tk) { return tk == 1 || tk == 2 || tk == 4 || tk == 6; }
 // Mixed precision on a term-list kind: escalation inside the FP32 launch (as on
 // the dense tables) or in a second, FP64 launch.  Without the FP64 stage in its
 // loop every term-list FP32 kernel fits 3 wavefronts per SIMD (168 VGPRs, 0-9
@@ -236,8 +236,9 @@ constexpr bool term_kind_inline_esc(int tk) { return tk == 1; }
 // The kind with the smallest solver that holds a term-list system.
 constexpr int term_kind_for(int max_deg, int n)
 {
-    return max_deg <= 2 ? (n <= 10 ? 5 : n <= 14 ? 3 : n <= 16 ? 0 : n <= 18 ? 4 : 2)
-                        : (n <= 16 ? 1 : n <= 18 ? 4 : 2);
+    return n > 20         ? 6
+           : max_deg <= 2 ? (n <= 10 ? 5 : n <= 14 ? 3 : n <= 16 ? 0 : n <= 18 ? 4 : 2)
+                          : (n <= 16 ? 1 : n <= 18 ? 4 : 2);
 }
 hipError_t launch_track_terms(int tk, bool fp32, const TrackArgs &a, hipStream_t st);
 hipError_t launch_track_queue_terms(int tk, bool fp32, bool param, const TrackArgs *jobs, const QueueItem *items,

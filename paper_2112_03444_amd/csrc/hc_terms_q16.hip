@@ -8,6 +8,7 @@ HC_TERMS_EXTERN(2)  // hc_terms_g20.hip
 HC_TERMS_EXTERN(3)  // hc_terms_q14.hip
 HC_TERMS_EXTERN(4)  // hc_terms_g18.hip
 HC_TERMS_EXTERN(5)  // hc_terms_q10.hip
+HC_TERMS_EXTERN(6)  // hc_terms_g32.hip
 
 namespace hcx {
 
@@ -21,6 +22,7 @@ hipError_t launch_track_terms(int tk, bool fp32, const TrackArgs &a, hipStream_t
     case 3: return launch_track_terms_k<3>(fp32, a, st);
     case 4: return launch_track_terms_k<4>(fp32, a, st);
     case 5: return launch_track_terms_k<5>(fp32, a, st);
+    case 6: return launch_track_terms_k<6>(fp32, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -35,6 +37,7 @@ hipError_t launch_track_queue_terms(int tk, bool fp32, bool param, const TrackAr
     case 3: return launch_track_queue_terms_k<3>(fp32, param, jobs, items, n_items, head, n_waves, st);
     case 4: return launch_track_queue_terms_k<4>(fp32, param, jobs, items, n_items, head, n_waves, st);
     case 5: return launch_track_queue_terms_k<5>(fp32, param, jobs, items, n_items, head, n_waves, st);
+    case 6: return launch_track_queue_terms_k<6>(fp32, param, jobs, items, n_items, head, n_waves, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -48,6 +51,7 @@ int queue_waves_terms(int tk, bool fp32, bool param)
     case 3: return queue_waves_terms_k<3>(fp32, param);
     case 4: return queue_waves_terms_k<4>(fp32, param);
     case 5: return queue_waves_terms_k<5>(fp32, param);
+    case 6: return queue_waves_terms_k<6>(fp32, param);
     default: return 0;
     }
 }
@@ -61,6 +65,7 @@ hipError_t launch_refine_terms(int tk, const RefineArgs &a, hipStream_t st)
     case 3: return launch_refine_terms_k<3>(&a, 1, a.total, false, st);
     case 4: return launch_refine_terms_k<4>(&a, 1, a.total, false, st);
     case 5: return launch_refine_terms_k<5>(&a, 1, a.total, false, st);
+    case 6: return launch_refine_terms_k<6>(&a, 1, a.total, false, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -74,6 +79,7 @@ hipError_t launch_refine_terms_many(int tk, const RefineArgs *a, int count, long
     case 3: return launch_refine_terms_k<3>(a, count, max_total, true, st);
     case 4: return launch_refine_terms_k<4>(a, count, max_total, true, st);
     case 5: return launch_refine_terms_k<5>(a, count, max_total, true, st);
+    case 6: return launch_refine_terms_k<6>(a, count, max_total, true, st);
     default: return hipErrorInvalidValue;
     }
 }

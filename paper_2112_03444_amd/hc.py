@@ -26,7 +26,7 @@ HC_FP64, HC_MIXED = 0, 1
  HC_T_REFINE_FAILED, HC_T_SINGULAR_END) = range(8)
 STATUS_NAMES = ["SUCCESS", "AT_INFINITY", "MIN_STEP", "MAX_STEPS", "SINGULAR", "NONFINITE",
                 "REFINE_FAILED", "SINGULAR_END"]
-HC_MAX_N = 20
+HC_MAX_N = 32
 HC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed workspace of hc_track_device_noalloc, per device
 HC_LAYOUT_AUTO, HC_LAYOUT_DENSE, HC_LAYOUT_TERMS = 0, 1, 2
 HC_EVAL_ROWS, HC_EVAL_MFMA = 0, 1

@@ -1,6 +1,6 @@
 """Parity of the general-degree term-list kernels (terms of degree up to 8,
-n <= 16 with 16 lanes per path, n <= 20 with 32) with the CPU oracle, on the
-GPU, through the C ABI.
+n <= 16 with 16 lanes per path, n <= 20 and n <= 32 with 32) with the CPU
+oracle, on the GPU, through the C ABI.
 
 Systems are dense on chosen supports (equation i: every monomial of degree
 <= d_i in the unknowns V_i, CN(0, 1) coefficients), so the total-degree
@@ -61,7 +61,8 @@ def linear_rows(n, count):
     return [(1, list(range(n)))] * count
 
 
-# (n, spec): kinds 1 (any degree, n <= 16), 4 (n 17..18) and 2 (n 19..20), and the
+# (n, spec): kinds 1 (any degree, n <= 16), 4 (n 17..18), 2 (n 19..20) and 6
+# (n 21..32: the paper's largest Jacobian is 32 x 32, section 1), and the
 # quadratic kind 0 (n 15..16)
 SPECS = {
     "cubic3": (3, [(3, [0, 1, 2])] * 3),
@@ -73,6 +74,9 @@ SPECS = {
     "cubic_n20": (20, [(3, [0, 1, 2]), (2, [0, 1, 2, 3])] + linear_rows(20, 18)),
     "quad_n17": (17, [(2, [0, 1, 2]), (2, [0, 1, 2])] + linear_rows(17, 15)),
     "quad_n15": (15, [(2, [0, 1, 2, 3]), (2, [0, 1, 2])] + linear_rows(15, 13)),
+    "cubic_n24": (24, [(3, [0, 1, 2]), (2, [0, 1, 2, 3])] + linear_rows(24, 22)),
+    "deg4_n32": (32, [(4, [0, 1]), (2, [0, 1, 2])] + linear_rows(32, 30)),
+    "quad_n32": (32, [(2, [0, 1, 2, 3])] * 4 + linear_rows(32, 28)),
 }
 
 
@@ -93,7 +97,7 @@ def test_total_degree_general(hc, ctx, name, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["mixed5", "deg5_n18"])
+@pytest.mark.parametrize("name", ["mixed5", "deg5_n18", "deg4_n32"])
 def test_parameter_homotopy_general(hc, ctx, name, precision):
     """Linear coefficient homotopy between two instances of one support: start
     points are the oracle's roots of instance 0 (section 3, parameter
@@ -110,7 +114,7 @@ def test_parameter_homotopy_general(hc, ctx, name, precision):
     assert np.all(info["residual"][st == hc.HC_T_SUCCESS] <= 1e-10)
 
 
-@pytest.mark.parametrize("name", ["cubic3", "mixed5", "deg5_n18"])
+@pytest.mark.parametrize("name", ["cubic3", "mixed5", "deg5_n18", "cubic_n24"])
 def test_fp64_residual_general(hc, ctx, name):
     """Mixed mode with the FP64 Newton right-hand side (fp64_residual) on the
     general-degree kinds, total degree: the same root sets as the oracle."""
@@ -186,6 +190,44 @@ def test_chunked_launches_general(hc, ctx):
     np.testing.assert_array_equal(a[0], b[0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_with_32_row_kind(hc, ctx, precision):
+    """The batch tracker (one device queue over jobs of several term-list kinds)
+    on jobs of the 32-row kind (n = 24 and 32) beside a g16 job: every job ends
+    with the statuses of a call on it alone and the oracle's root sets.  The
+    batch escalates inline, the single call of the 32-row kind in a second
+    launch; both run the same FP64 stages, so the endpoints agree to rounding."""
+    import torch
+    dev = torch.device("cuda:0")
+    opts = hc.default_opts(precision=precision)
+    jobs, refs, oin = [], [], []
+    for k, name in enumerate(["cubic_n24", "mixed5", "quad_n32"]):
+        n, spec = SPECS[name]
+        S, coef, gam = hc_inputs.support_instances(n, spec, 2, seed=6700 + k)
+        sysh = ctx.load_system(S)
+        ns = sysh.bezout
+        p = torch.from_numpy(coef).to(dev)
+        g = torch.from_numpy(gam).to(dev)
+        ep = torch.empty((2, ns, n), dtype=torch.complex128, device=dev)
+        st = torch.empty((2, ns), dtype=torch.int32, device=dev)
+        ctx.track_device(sysh, p, g, ep, st, None, opts=opts)
+        torch.cuda.synchronize()
+        refs.append((ep.cpu().numpy(), st.cpu().numpy()))
+        oin.append((S, coef, gam))
+        jobs.append(dict(sys=sysh, p_target=p, gamma=g, n_start=ns, endpoints=torch.zeros_like(ep),
+                         status=torch.zeros_like(st)))
+    ctx.track_batch_device(jobs, opts=opts)
+    torch.cuda.synchronize()
+    for j, (rep, rst), (S, coef, gam) in zip(jobs, refs, oin):
+        ep, st = j["endpoints"].cpu().numpy(), j["status"].cpu().numpy()
+        np.testing.assert_array_equal(st, rst)
+        ok = st == hc.HC_T_SUCCESS
+        np.testing.assert_allclose(ep[ok], rep[ok], rtol=1e-12, atol=1e-12)
+        oep, ost, _ = oracle.track(S, coef, gam)
+        for i in range(2):
+            check_parity(ep[i], st[i], oep[i], ost[i], hc)
+
+
 def test_general_load_errors(hc, ctx):
     deg9 = hc_inputs.support_system(2, [(9, [0]), (1, [0, 1])])
     with pytest.raises(hc.HcError):
@@ -194,7 +236,7 @@ def test_general_load_errors(hc, ctx):
     with pytest.raises(hc.HcError):
         ctx.load_system(cubic, layout=hc.HC_LAYOUT_DENSE)  # dense tables: degree <= 2
     with pytest.raises(hc.HcError):
-        ctx.load_system(hc_inputs.dense_quadratic_system(21))  # n > HC_MAX_N
+        ctx.load_system(hc_inputs.support_system(33, linear_rows(33, 33)))  # n > HC_MAX_N
     sysh = ctx.load_system(hc_inputs.support_system(*SPECS["deg5_n18"]))
     _, coef, gam = hc_inputs.support_instances(*SPECS["deg5_n18"], 1, seed=6500)
     with pytest.raises(hc.HcError):

@@ -239,9 +239,10 @@ def test_path_at_infinity(hc, ctx):
 
 
 def test_load_system_errors(hc, ctx):
-    S21 = hc_inputs.dense_quadratic_system(21)
+    assert hc.HC_MAX_N == 32  # the paper's largest Jacobian, 32 x 32 (section 1)
+    S33 = hc_inputs.support_system(33, [(1, list(range(33)))] * 33)
     with pytest.raises(hc.HcError):
-        ctx.load_system(S21)  # n > HC_MAX_N
+        ctx.load_system(S33)  # n > HC_MAX_N
     with pytest.raises(hc.HcError):
         ctx.load_system(hc_inputs.dense_quadratic_system(9), layout=hc.HC_LAYOUT_DENSE)  # dense tables: n <= 8
     with pytest.raises(hc.HcError):
