@@ -770,7 +770,42 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
     }
     const R omt = R(1) - t;
     cx<R> F = zero;
-    if constexpr (!TermCfg<TK>::GEN) {
+    if constexpr (!TermCfg<TK>::GEN && NM < TermCfg<TK>::G) {
+        // q10, q14: lane NM of the group publishes 1 at xg[NM], and entry NM of
+        // every row accumulator is padding, so a missing factor (0xFF) reads
+        // index NM and the slot needs no branch.  The next slot's variables
+        // and coefficients are loaded while this one is evaluated.
+        using gptr = const __attribute__((address_space(1))) R *;
+        const gptr g1 = (gptr)c1, g0 = (gptr)c0;
+        const unsigned short *vr = static_cast<const unsigned short *>(vars);
+        const int cnt = own ? T : 0;
+        unsigned vn = cnt > 0 ? vr[0] : 0xFFFFu;
+        cx<R> c1n = cnt > 0 ? cx<R>{g1[0], g1[1]} : zero, c0n = zero;
+        if constexpr (PARAM) c0n = cnt > 0 ? cx<R>{g0[0], g0[1]} : zero;
+        for (int k = 0; k < cnt; k++) {
+            const unsigned v = vn;
+            const cx<R> c = c1n, s0 = c0n;
+            if (k + 1 < cnt) {
+                vn = vr[k + 1];
+                c1n = {g1[2 * k + 2], g1[2 * k + 3]};
+                if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
+            }
+            const int ia = min((int)(v & 0xFFu), NM), ib = min((int)(v >> 8), NM);
+            cx<R> ct = c, cr = c;
+            if constexpr (PARAM) {
+                ct = {fma(t, c.re, omt * s0.re), fma(t, c.im, omt * s0.im)};
+                cr = pred ? cx<R>{c.re - s0.re, c.im - s0.im} : ct;
+            }
+            const cx<R> xa = ldl(xg, ia), xb = ldl(xg, ib);
+            const cx<R> ra = ldl(rb, ia), rbb = ldl(rb, ib);
+            F = cfma(cr, cmul(xa, xb), F);
+            // x_a^2 (ia == ib): the second write carries both contributions
+            const cx<R> na = cfma(ct, xb, ra);
+            const cx<R> nb = cfma(ct, xa, ia == ib ? na : rbb);
+            stl(rb, ia, na);
+            stl(rb, ib, nb);
+        }
+    } else if constexpr (!TermCfg<TK>::GEN) {
         const unsigned short *vr = static_cast<const unsigned short *>(vars);
         const int cnt = own ? T : 0;
         for (int k = 0; k < cnt; k++) {
@@ -895,7 +930,9 @@ __device__ __forceinline__ bool stage_solve_terms(const void *vars, const int *s
 {
     constexpr int NM = TermCfg<TK>::NM, G = TermCfg<TK>::G;
     const lds_tab<R> xs = (lds_tab<R>)(cx<R> *)ldsv;
-    const cx<R> xo = own ? cx<R>{R(xe.re), R(xe.im)} : cx<R>{R(0), R(0)};
+    // q10, q14: lane NM of the group holds 1, the value of a missing factor
+    const R pad = (!TermCfg<TK>::GEN && NM < G && r == NM) ? R(1) : R(0);
+    const cx<R> xo = own ? cx<R>{R(xe.re), R(xe.im)} : cx<R>{pad, R(0)};
     stl(xs, lane, xo);
     const bool use_ir = sizeof(R) == 4 && ir && !pred;
     const lds_tab<double> x64 =
