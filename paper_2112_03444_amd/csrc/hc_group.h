@@ -698,7 +698,11 @@ __device__ __forceinline__ lds_tab<R> terms_row_acc(lds_tab<R> xs, int base, int
 // together (one LDS round trip per term, not one per factor); a repeated
 // variable's contributions are summed into the last factor of its run, the
 // only one written.
-template <int D, int NM, typename R>
+//
+// PADL (kinds with NM < G): lane NM of the group holds 1 at xg[NM] and entry
+// NM of the row accumulator is padding, so a missing factor reads and writes
+// index NM instead of being selected around.
+template <int D, int NM, typename R, bool PADL>
 __device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<R> ct, lds_tab<R> xg, lds_tab<R> rb,
                                              cx<R> &F)
 {
@@ -708,8 +712,14 @@ __device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<
 #pragma unroll
     for (int i = 0; i < D; i++) {
         f[i] = (int)((v >> (8 * i)) & 0xFFull);
-        xv[i] = f[i] < NM ? ldl(xg, f[i]) : one;
-        acc[i] = f[i] < NM ? ldl(rb, f[i]) : zero;
+        if constexpr (PADL) {
+            f[i] = min(f[i], NM);
+            xv[i] = ldl(xg, f[i]);
+            acc[i] = ldl(rb, f[i]);
+        } else {
+            xv[i] = f[i] < NM ? ldl(xg, f[i]) : one;
+            acc[i] = f[i] < NM ? ldl(rb, f[i]) : zero;
+        }
     }
     cx<R> P[D];  // P[i] = x_{f_0} ... x_{f_{i-1}}
     P[0] = one;
@@ -728,7 +738,7 @@ __device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<
     for (int i = 0; i < D; i++) {
         run = cfma(ct, dm[i], run);
         const bool last = i == D - 1 || f[i + 1] != f[i];
-        if (f[i] < NM && last) stl(rb, f[i], cx<R>{acc[i].re + run.re, acc[i].im + run.im});
+        if ((PADL || f[i] < NM) && last) stl(rb, f[i], cx<R>{acc[i].re + run.re, acc[i].im + run.im});
         if (last) run = zero;
     }
 }
@@ -827,22 +837,39 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
             }
         }
     } else if (own) {
+        // the next slot's variables and coefficients are loaded while this one is
+        // evaluated
+        constexpr bool PADL = NM < TermCfg<TK>::G;
+        using gptr = const __attribute__((address_space(1))) R *;
+        const gptr g1 = (gptr)c1, g0 = (gptr)c0;
         const unsigned long long *vr = static_cast<const unsigned long long *>(vars);
+        unsigned long long vn = T > 0 ? vr[0] : ~0ull;
+        cx<R> c1n = T > 0 ? cx<R>{g1[0], g1[1]} : zero, c0n = zero;
+        if constexpr (PARAM) c0n = T > 0 ? cx<R>{g0[0], g0[1]} : zero;
         for (int k = 0; k < T; k++) {
             const int m = __builtin_amdgcn_readfirstlane(sdeg[k]);  // same slot in every lane
-            const unsigned long long v = vr[k];
-            cx<R> ct, cr;
-            slot_coefs<R, PARAM>(c1, c0, k, t, omt, pred, ct, cr);
+            const unsigned long long v = vn;
+            const cx<R> c = c1n, s0 = c0n;
+            if (k + 1 < T) {
+                vn = vr[k + 1];
+                c1n = {g1[2 * k + 2], g1[2 * k + 3]};
+                if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
+            }
+            cx<R> ct = c, cr = c;
+            if constexpr (PARAM) {
+                ct = {fma(t, c.re, omt * s0.re), fma(t, c.im, omt * s0.im)};
+                cr = pred ? cx<R>{c.re - s0.re, c.im - s0.im} : ct;
+            }
             switch (m) {
             case 0: F = cfma(cr, one, F); break;
-            case 1: term_general<1, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 2: term_general<2, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 3: term_general<3, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 4: term_general<4, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 5: term_general<5, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 6: term_general<6, NM, R>(v, cr, ct, xg, rb, F); break;
-            case 7: term_general<7, NM, R>(v, cr, ct, xg, rb, F); break;
-            default: term_general<8, NM, R>(v, cr, ct, xg, rb, F); break;
+            case 1: term_general<1, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 2: term_general<2, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 3: term_general<3, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 4: term_general<4, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 5: term_general<5, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 6: term_general<6, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            case 7: term_general<7, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
+            default: term_general<8, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
             }
         }
     }
@@ -930,8 +957,9 @@ __device__ __forceinline__ bool stage_solve_terms(const void *vars, const int *s
 {
     constexpr int NM = TermCfg<TK>::NM, G = TermCfg<TK>::G;
     const lds_tab<R> xs = (lds_tab<R>)(cx<R> *)ldsv;
-    // q10, q14: lane NM of the group holds 1, the value of a missing factor
-    const R pad = (!TermCfg<TK>::GEN && NM < G && r == NM) ? R(1) : R(0);
+    // kinds with NM < G (q10, q14, g18, g20): lane NM of the group holds 1, the
+    // value of a missing factor
+    const R pad = (NM < G && r == NM) ? R(1) : R(0);
     const cx<R> xo = own ? cx<R>{R(xe.re), R(xe.im)} : cx<R>{pad, R(0)};
     stl(xs, lane, xo);
     const bool use_ir = sizeof(R) == 4 && ir && !pred;
