@@ -13,8 +13,8 @@
 // quadratic part, as in the group trackers), and each elimination step of the
 // LU with partial pivoting (section 6: the augmented matrix, then back
 // substitution with U) is one multiply-add per lane after a pivot search over
-// column k (readlane of the 8 candidates) and one LDS exchange of the pivot row
-// and the multipliers' column.  The path state (x, t, h, counters) is uniform
+// column k (readlane of the 8 candidates) and an exchange of the pivot row and
+// the multipliers' column across lanes (ds_bpermute, readlane).  The path state (x, t, h, counters) is uniform
 // across the wavefront; every lane takes the same decisions.
 //
 // Same stage machine, step control and statuses as the group trackers (RK4
@@ -29,15 +29,23 @@ namespace {
 
 template <int N>
 struct WaveLds {
-    cx<double> row[N + 1];  // the pivot row's entries (and its right-hand side)
-    cx<double> col[8];      // column k of every row (the multipliers' numerators)
     cx<double> u[N][N + 1]; // rows of U in pivot order, then back substitution
 };
 
 // Orders this wavefront's LDS accesses around it in program order only: a
-// wavefront's LDS instructions execute in issue order, so a write after the
-// reads of the previous exchange cannot overtake them.
+// wavefront's LDS instructions execute in issue order, so the back substitution
+// reads the rows of U the elimination wrote, and the next stage's writes cannot
+// overtake this stage's reads.
 __device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+// Lane src's value of v in every lane (src per lane, in range).
+__device__ __forceinline__ double bperm(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 __device__ __forceinline__ double rdl(double v, int src)
 {
@@ -71,13 +79,6 @@ __device__ __forceinline__ double row_sum(double v)
 __device__ __forceinline__ cx<double> pick(bool s, cx<double> a, cx<double> b)
 {
     return {s ? a.re : b.re, s ? a.im : b.im};
-}
-
-__device__ __forceinline__ void lds_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // The coefficients lane (i, j) needs, read once per path from the instance's
@@ -164,19 +165,18 @@ __device__ __forceinline__ bool wave_stage(const WaveCoef<N> &w, cx<double> gam,
         const int p = 7 - (int)(best & 7u);
         sing |= (best & ~7u) == 0u;
         piv |= 1u << p;
-        // the pivot row and column k through LDS; the pivot row is also row k of
-        // U (in pivot order) for the back substitution
-        if (i == p && j >= k && j < N) {
-            L.row[j] = a;
-            L.u[k][j] = a;
-        }
-        if (i == p && j == 0) {
-            L.row[N] = rhs;
-            L.u[k][N] = rhs;
-        }
-        if (j == k) L.col[i] = a;
-        lds_fence();
-        const cx<double> pr = L.row[jj], pb = L.row[N], pk = L.row[k], aik = L.col[i];
+        // the pivot row is row k of U (in pivot order) for the back
+        // substitution, which reads it after the elimination: stored now, no
+        // wait here
+        if (i == p && j >= k && j < N) L.u[k][j] = a;
+        if (i == p && j == 0) L.u[k][N] = rhs;
+        // the pivot row's entries and column k reach every lane across the
+        // wavefront's lanes (ds_bpermute, and readlane for the uniform pivot
+        // and right-hand side) rather than through an LDS round trip
+        const cx<double> pk = {rdl(a.re, p * 8 + k), rdl(a.im, p * 8 + k)};
+        const cx<double> pb = {rdl(rhs.re, p * 8), rdl(rhs.im, p * 8)};
+        const cx<double> pr = {bperm(a.re, p * 8 + jj), bperm(a.im, p * 8 + jj)};
+        const cx<double> aik = {bperm(a.re, ii * 8 + k), bperm(a.im, ii * 8 + k)};
         inv[k] = crecip(pk);
         const cx<double> l = cmul(aik, inv[k]);
         if (!((piv >> i) & 1u) && i < N) {
