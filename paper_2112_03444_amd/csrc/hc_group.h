@@ -783,19 +783,31 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
     if constexpr (!TermCfg<TK>::GEN && NM < TermCfg<TK>::G) {
         // q10, q14: lane NM of the group publishes 1 at xg[NM], and entry NM of
         // every row accumulator is padding, so a missing factor (0xFF) reads
-        // index NM and the slot needs no branch.  The next slot's variables
-        // and coefficients are loaded while this one is evaluated.
+        // index NM and the slot needs no branch.  FP32: the next slot's
+        // variables and coefficients are loaded while this one is evaluated;
+        // FP64 loads them at the top of the slot (the prefetched FP64 values
+        // cost spills at 3 wavefronts per SIMD and measured ~1% slower).
         using gptr = const __attribute__((address_space(1))) R *;
         const gptr g1 = (gptr)c1, g0 = (gptr)c0;
         const unsigned short *vr = static_cast<const unsigned short *>(vars);
         const int cnt = own ? T : 0;
-        unsigned vn = cnt > 0 ? vr[0] : 0xFFFFu;
-        cx<R> c1n = cnt > 0 ? cx<R>{g1[0], g1[1]} : zero, c0n = zero;
-        if constexpr (PARAM) c0n = cnt > 0 ? cx<R>{g0[0], g0[1]} : zero;
+        constexpr bool PREF = sizeof(R) == 4;
+        unsigned vn = 0xFFFFu;
+        cx<R> c1n = zero, c0n = zero;
+        if constexpr (PREF) {
+            vn = cnt > 0 ? vr[0] : 0xFFFFu;
+            c1n = cnt > 0 ? cx<R>{g1[0], g1[1]} : zero;
+            if constexpr (PARAM) c0n = cnt > 0 ? cx<R>{g0[0], g0[1]} : zero;
+        }
         for (int k = 0; k < cnt; k++) {
+            if constexpr (!PREF) {
+                vn = vr[k];
+                c1n = {g1[2 * k], g1[2 * k + 1]};
+                if constexpr (PARAM) c0n = {g0[2 * k], g0[2 * k + 1]};
+            }
             const unsigned v = vn;
             const cx<R> c = c1n, s0 = c0n;
-            if (k + 1 < cnt) {
+            if (PREF && k + 1 < cnt) {
                 vn = vr[k + 1];
                 c1n = {g1[2 * k + 2], g1[2 * k + 3]};
                 if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
@@ -837,20 +849,30 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
             }
         }
     } else if (own) {
-        // the next slot's variables and coefficients are loaded while this one is
-        // evaluated
+        // FP32: the next slot's variables and coefficients are loaded while this
+        // one is evaluated (FP64 loads them at the top of the slot, as above)
         constexpr bool PADL = NM < TermCfg<TK>::G;
         using gptr = const __attribute__((address_space(1))) R *;
         const gptr g1 = (gptr)c1, g0 = (gptr)c0;
         const unsigned long long *vr = static_cast<const unsigned long long *>(vars);
-        unsigned long long vn = T > 0 ? vr[0] : ~0ull;
-        cx<R> c1n = T > 0 ? cx<R>{g1[0], g1[1]} : zero, c0n = zero;
-        if constexpr (PARAM) c0n = T > 0 ? cx<R>{g0[0], g0[1]} : zero;
+        constexpr bool PREF = sizeof(R) == 4;
+        unsigned long long vn = ~0ull;
+        cx<R> c1n = zero, c0n = zero;
+        if constexpr (PREF) {
+            vn = T > 0 ? vr[0] : ~0ull;
+            c1n = T > 0 ? cx<R>{g1[0], g1[1]} : zero;
+            if constexpr (PARAM) c0n = T > 0 ? cx<R>{g0[0], g0[1]} : zero;
+        }
         for (int k = 0; k < T; k++) {
             const int m = __builtin_amdgcn_readfirstlane(sdeg[k]);  // same slot in every lane
+            if constexpr (!PREF) {
+                vn = vr[k];
+                c1n = {g1[2 * k], g1[2 * k + 1]};
+                if constexpr (PARAM) c0n = {g0[2 * k], g0[2 * k + 1]};
+            }
             const unsigned long long v = vn;
             const cx<R> c = c1n, s0 = c0n;
-            if (k + 1 < T) {
+            if (PREF && k + 1 < T) {
                 vn = vr[k + 1];
                 c1n = {g1[2 * k + 2], g1[2 * k + 3]};
                 if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
