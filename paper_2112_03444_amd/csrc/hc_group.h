@@ -743,18 +743,16 @@ __device__ __forceinline__ void term_general(unsigned long long v, cx<R> cr, cx<
     }
 }
 
-// Coefficient of slot k at t (ct, for the Jacobian and H) and on the right-hand
-// side (cr): c1 for total degree; (1-t) c0 + t c1, and c1 - c0 for H_t in a
-// predictor stage, for a parameter homotopy.
+// Coefficient of a slot at t (ct, for the Jacobian and H) and on the right-hand
+// side (cr), from its target value c (c1) and start value s (c0): c for total
+// degree; (1-t) s + t c, and c - s for H_t in a predictor stage, for a
+// parameter homotopy.
 template <typename R, bool PARAM>
-__device__ __forceinline__ void slot_coefs(const R *c1, const R *c0, int k, R t, R omt, bool pred, cx<R> &ct,
-                                           cx<R> &cr)
+__device__ __forceinline__ void slot_coefs(cx<R> c, cx<R> s, R t, R omt, bool pred, cx<R> &ct, cx<R> &cr)
 {
-    const cx<R> c = {c1[2 * k], c1[2 * k + 1]};
     ct = c;
     cr = c;
     if constexpr (PARAM) {
-        const cx<R> s = {c0[2 * k], c0[2 * k + 1]};
         ct = {fma(t, c.re, omt * s.re), fma(t, c.im, omt * s.im)};
         cr = pred ? cx<R>{c.re - s.re, c.im - s.im} : ct;
     }
@@ -780,18 +778,21 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
     }
     const R omt = R(1) - t;
     cx<R> F = zero;
-    if constexpr (!TermCfg<TK>::GEN && NM < TermCfg<TK>::G) {
-        // q10, q14: lane NM of the group publishes 1 at xg[NM], and entry NM of
-        // every row accumulator is padding, so a missing factor (0xFF) reads
-        // index NM and the slot needs no branch.  FP32: the next slot's
-        // variables and coefficients are loaded while this one is evaluated;
-        // FP64 loads them at the top of the slot (the prefetched FP64 values
-        // cost spills at 3 wavefronts per SIMD and measured ~1% slower).
+    if constexpr (!TermCfg<TK>::GEN) {
+        // q10, q14 (NM < G): lane NM of the group publishes 1 at xg[NM], and
+        // entry NM of every row accumulator is padding, so a missing factor
+        // (0xFF) reads index NM and the slot needs no branch; q16 selects around
+        // a missing factor.  A squared variable's two contributions go through
+        // the second write.  FP32: the next slot's variables and coefficients
+        // are loaded while this one is evaluated; FP64 loads them at the top of
+        // the slot (the prefetched FP64 values cost spills at 3 wavefronts per
+        // SIMD and measured ~1% slower).
+        constexpr bool PADQ = NM < TermCfg<TK>::G;
+        constexpr bool PREF = sizeof(R) == 4;
         using gptr = const __attribute__((address_space(1))) R *;
         const gptr g1 = (gptr)c1, g0 = (gptr)c0;
         const unsigned short *vr = static_cast<const unsigned short *>(vars);
         const int cnt = own ? T : 0;
-        constexpr bool PREF = sizeof(R) == 4;
         unsigned vn = 0xFFFFu;
         cx<R> c1n = zero, c0n = zero;
         if constexpr (PREF) {
@@ -812,41 +813,31 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
                 c1n = {g1[2 * k + 2], g1[2 * k + 3]};
                 if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
             }
-            const int ia = min((int)(v & 0xFFu), NM), ib = min((int)(v >> 8), NM);
-            cx<R> ct = c, cr = c;
-            if constexpr (PARAM) {
-                ct = {fma(t, c.re, omt * s0.re), fma(t, c.im, omt * s0.im)};
-                cr = pred ? cx<R>{c.re - s0.re, c.im - s0.im} : ct;
+            int ia = (int)(v & 0xFFu), ib = (int)(v >> 8);
+            if constexpr (PADQ) {
+                ia = min(ia, NM);
+                ib = min(ib, NM);
             }
-            const cx<R> xa = ldl(xg, ia), xb = ldl(xg, ib);
-            const cx<R> ra = ldl(rb, ia), rbb = ldl(rb, ib);
+            cx<R> ct, cr;
+            slot_coefs<R, PARAM>(c, s0, t, omt, pred, ct, cr);
+            cx<R> xa, xb, ra, rbb;
+            if constexpr (PADQ) {
+                xa = ldl(xg, ia);
+                xb = ldl(xg, ib);
+                ra = ldl(rb, ia);
+                rbb = ldl(rb, ib);
+            } else {
+                xa = ia < NM ? ldl(xg, ia) : one;
+                xb = ib < NM ? ldl(xg, ib) : one;
+                ra = ia < NM ? ldl(rb, ia) : zero;
+                rbb = ib < NM ? ldl(rb, ib) : zero;
+            }
             F = cfma(cr, cmul(xa, xb), F);
             // x_a^2 (ia == ib): the second write carries both contributions
             const cx<R> na = cfma(ct, xb, ra);
             const cx<R> nb = cfma(ct, xa, ia == ib ? na : rbb);
-            stl(rb, ia, na);
-            stl(rb, ib, nb);
-        }
-    } else if constexpr (!TermCfg<TK>::GEN) {
-        const unsigned short *vr = static_cast<const unsigned short *>(vars);
-        const int cnt = own ? T : 0;
-        for (int k = 0; k < cnt; k++) {
-            const unsigned v = vr[k];
-            const int ia = (int)(v & 0xFFu), ib = (int)(v >> 8);
-            cx<R> ct, cr;
-            slot_coefs<R, PARAM>(c1, c0, k, t, omt, pred, ct, cr);
-            const cx<R> xa = ia < NM ? ldl(xg, ia) : one;
-            const cx<R> xb = ib < NM ? ldl(xg, ib) : one;
-            // both accumulator entries read, then written (x_a^2: one entry)
-            const cx<R> ra = ia < NM ? ldl(rb, ia) : zero;
-            const cx<R> rbb = ib < NM ? ldl(rb, ib) : zero;
-            F = cfma(cr, cmul(xa, xb), F);
-            if (ia == ib) {
-                if (ia < NM) stl(rb, ia, cfma(ct, xa, cfma(ct, xb, ra)));
-            } else {
-                if (ia < NM) stl(rb, ia, cfma(ct, xb, ra));
-                if (ib < NM) stl(rb, ib, cfma(ct, xa, rbb));
-            }
+            if (PADQ || ia < NM) stl(rb, ia, na);
+            if (PADQ || ib < NM) stl(rb, ib, nb);
         }
     } else if (own) {
         // FP32: the next slot's variables and coefficients are loaded while this
@@ -877,11 +868,8 @@ __device__ __forceinline__ void build_row_terms(const void *vars, const int *sde
                 c1n = {g1[2 * k + 2], g1[2 * k + 3]};
                 if constexpr (PARAM) c0n = {g0[2 * k + 2], g0[2 * k + 3]};
             }
-            cx<R> ct = c, cr = c;
-            if constexpr (PARAM) {
-                ct = {fma(t, c.re, omt * s0.re), fma(t, c.im, omt * s0.im)};
-                cr = pred ? cx<R>{c.re - s0.re, c.im - s0.im} : ct;
-            }
+            cx<R> ct, cr;
+            slot_coefs<R, PARAM>(c, s0, t, omt, pred, ct, cr);
             switch (m) {
             case 0: F = cfma(cr, one, F); break;
             case 1: term_general<1, NM, R, PADL>(v, cr, ct, xg, rb, F); break;
