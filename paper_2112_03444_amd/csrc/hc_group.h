@@ -1029,9 +1029,20 @@ __device__ __attribute__((noinline)) StageOut stage64_terms(const void *vars, co
 // accepted point, h reset to h0 after a failure) -- the wavefront runs the FP64
 // stage, with tables read from global memory, only while one of its groups
 // needs it.
-template <int N, int G, typename R, bool PARAM, typename Src, int TK = -1, int ESC = -1>
+template <int N, int G, typename R, bool PARAM, typename Src, int TK = -1, int ESC = -1, bool KARG = false>
 __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *lds)
 {
+    // KARG: `a` is the kernel's only argument, so the loop reads the launch
+    // constants and state pointers it needs per stage from the kernel-argument
+    // segment where it uses them (scalar loads) instead of holding them in
+    // scalar registers across the loop, which spilled them to vector lanes
+    using kargp = const __attribute__((address_space(4))) TrackArgs *;
+    auto kap = []() {
+        kargp p = (kargp)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(p));
+        return p;
+    };
+#define HC_ARG(f) (KARG ? kap()->f : a.f)
     constexpr bool TERMS = TK >= 0;
     constexpr int TKc = TERMS ? TK : 0;
     static_assert(G == 4 || G == 8 || G == 16 || G == 32, "group size");
@@ -1061,7 +1072,6 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     // mixed precision: FP64 corrector right-hand side around the FP32 solves
     const bool ir = !R64 && a.ir;
     const long long total = a.total;
-    const TrackState S = a.s;
     const double pred_tol = a.pred_tol;
     const bool d2 = own && ((a.deg2 >> r) & 1u);
     // term lists: degree of the lane's equation (total-degree start system)
@@ -1093,21 +1103,21 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
 
     auto save = [&](int st) {
         if (own) {
-            S.xr[r * total + g] = x.re;
-            S.xi[r * total + g] = x.im;
+            HC_ARG(s.xr)[r * total + g] = x.re;
+            HC_ARG(s.xi)[r * total + g] = x.im;
         }
         if (r == 0) {
-            S.t[g] = t;
-            S.h[g] = h;
-            S.succ[g] = succ;
-            S.steps[g] = steps;
-            S.rejects[g] = rejects;
-            S.nits[g] = nits;
-            S.escal[g] = escal;
-            S.status[g] = st;
-            if (a.stage_count) {
-                if (lst32) atomicAdd(a.stage_count, (unsigned long long)lst32);
-                if (lst64) atomicAdd(a.stage_count + 1, (unsigned long long)lst64);
+            HC_ARG(s.t)[g] = t;
+            HC_ARG(s.h)[g] = h;
+            HC_ARG(s.succ)[g] = succ;
+            HC_ARG(s.steps)[g] = steps;
+            HC_ARG(s.rejects)[g] = rejects;
+            HC_ARG(s.nits)[g] = nits;
+            HC_ARG(s.escal)[g] = escal;
+            HC_ARG(s.status)[g] = st;
+            if (HC_ARG(stage_count)) {
+                if (lst32) atomicAdd(HC_ARG(stage_count), (unsigned long long)lst32);
+                if (lst64) atomicAdd(HC_ARG(stage_count) + 1, (unsigned long long)lst64);
             }
         }
         lst32 = lst64 = 0;
@@ -1115,7 +1125,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
     };
     auto begin_step = [&]() {
         // an FP32 step ends at t_switch at the latest
-        const double tf = p64 ? a.t_final : a.t_switch;
+        const double tf = p64 ? HC_ARG(t_final) : HC_ARG(t_switch);
         const double rem = tf - t;
         if (h >= rem) {
             hu = rem;
@@ -1133,14 +1143,14 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
             // mixed precision: the path goes on in FP64 from its last accepted point,
             // in this launch or (escalation off) in the FP64 launch that follows
             escal = steps + rejects + 1;
-            h = a.h0;
+            h = HC_ARG(h0);
             succ = 0;
             if (!kInl) {
                 save(kRunning);
                 return;
             }
             p64 = true;
-            if (steps_used(steps, rejects, escal) >= a.max_steps)
+            if (steps_used(steps, rejects, escal) >= HC_ARG(max_steps))
                 save(HC_T_MAX_STEPS);
             else
                 begin_step();
@@ -1173,8 +1183,8 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
             if (trk < 0 && cand < tend) {
                 const long long gg = (long long)cur_inst * a.n_start + cand;
                 // still going and not yet at this launch's end time
-                if (S.status[gg] == kRunning && S.t[gg] < a.t_final &&
-                    (R64 || kInl || S.escal[gg] == 0)) {
+                if (HC_ARG(s.status)[gg] == kRunning && HC_ARG(s.t)[gg] < HC_ARG(t_final) &&
+                    (R64 || kInl || HC_ARG(s.escal)[gg] == 0)) {
                     trk = cand;
                     g = gg;
                     gslot = cur_slot;
@@ -1190,17 +1200,17 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                         row0 = static_cast<const R *>(a.coef0) + ro0;
                         if (!R64) row0_64 = static_cast<const double *>(a.coef0_64) + ro0;
                     }
-                    x = own ? cx<double>{S.xr[r * total + g], S.xi[r * total + g]} : cx<double>{0.0, 0.0};
-                    t = S.t[g];
-                    h = S.h[g];
-                    succ = S.succ[g];
-                    steps = S.steps[g];
-                    rejects = S.rejects[g];
-                    nits = S.nits[g];
-                    escal = S.escal[g];
-                    p64 = R64 || (kInl && (escal != 0 || t >= a.t_switch));
+                    x = own ? cx<double>{HC_ARG(s.xr)[r * total + g], HC_ARG(s.xi)[r * total + g]} : cx<double>{0.0, 0.0};
+                    t = HC_ARG(s.t)[g];
+                    h = HC_ARG(s.h)[g];
+                    succ = HC_ARG(s.succ)[g];
+                    steps = HC_ARG(s.steps)[g];
+                    rejects = HC_ARG(s.rejects)[g];
+                    nits = HC_ARG(s.nits)[g];
+                    escal = HC_ARG(s.escal)[g];
+                    p64 = R64 || (kInl && (escal != 0 || t >= HC_ARG(t_switch)));
                     lsteps = 0;
-                    if (steps_used(steps, rejects, escal) >= a.max_steps)
+                    if (steps_used(steps, rejects, escal) >= HC_ARG(max_steps))
                         fail(HC_T_MAX_STEPS);
                     else
                         begin_step();
@@ -1255,7 +1265,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 lst64++;
             else
                 lst32++;
-            const double tau = p64 ? a.tau64 : a.tau;
+            const double tau = p64 ? HC_ARG(tau64) : HC_ARG(tau);
             // 0: stage done, 1: accept the step, 2: reject it, 3: path failed (fst)
             int ev = 0, fst = 0;
             if (phase < 4) {
@@ -1274,7 +1284,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     te = phase == 0 || phase == 1 ? t + 0.5 * hu : tn;
                     nit = 0;
                     phase++;
-                    if (phase == 4 && a.max_newton <= 0) ev = 2;
+                    if (phase == 4 && HC_ARG(max_newton) <= 0) ev = 2;
                 }
             } else if (sing) {
                 ev = 2;
@@ -1288,7 +1298,7 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                     ev = 2;
                 else if (nd <= tau * (1.0 + nx))
                     ev = 1;
-                else if (nit >= a.max_newton)
+                else if (nit >= HC_ARG(max_newton))
                     ev = 2;
             }
             bool next_step = false;
@@ -1297,26 +1307,26 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 t = tn;
                 steps++;
                 lsteps++;
-                if (++succ >= a.n_inc) {
-                    h = fmin(h * a.beta_inc, a.h_max);
+                if (++succ >= HC_ARG(n_inc)) {
+                    h = fmin(h * HC_ARG(beta_inc), HC_ARG(h_max));
                     succ = 0;
                 }
                 const double m2 = abs2(x);
-                if (group_any<G>(!(m2 <= a.inf2), base)) {
+                if (group_any<G>(!(m2 <= HC_ARG(inf2)), base)) {
                     ev = 3;
                     fst = group_any<G>(isnan(m2), base) ? HC_T_NONFINITE : HC_T_AT_INFINITY;
-                } else if (t >= a.t_final) {
-                    save(a.t_final >= 1.0 ? kReached : kRunning);
+                } else if (t >= HC_ARG(t_final)) {
+                    save(HC_ARG(t_final) >= 1.0 ? kReached : kRunning);
                 } else {
-                    if (!p64 && t >= a.t_switch) p64 = true;  // FP64 end zone
+                    if (!p64 && t >= HC_ARG(t_switch)) p64 = true;  // FP64 end zone
                     next_step = true;
                 }
             } else if (ev == 2) {
                 rejects++;
                 lsteps++;
                 succ = 0;
-                h *= a.beta_dec;
-                if (h < a.h_min) {
+                h *= HC_ARG(beta_dec);
+                if (h < HC_ARG(h_min)) {
                     ev = 3;
                     fst = HC_T_MIN_STEP;
                 } else {
@@ -1324,10 +1334,10 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
                 }
             }
             if (next_step) {
-                if (a.launch_steps > 0 && lsteps >= a.launch_steps) {
-                    if (r == 0) atomicAdd(a.n_suspended, 1u);
+                if (HC_ARG(launch_steps) > 0 && lsteps >= HC_ARG(launch_steps)) {
+                    if (r == 0) atomicAdd(HC_ARG(n_suspended), 1u);
                     save(kRunning);
-                } else if (steps_used(steps, rejects, escal) >= a.max_steps) {
+                } else if (steps_used(steps, rejects, escal) >= HC_ARG(max_steps)) {
                     ev = 3;
                     fst = HC_T_MAX_STEPS;
                 } else {
@@ -1339,5 +1349,6 @@ __device__ __forceinline__ void run_items(const TrackArgs &a, Src &src, cx<R> *l
         refill();
     }
 }
+#undef HC_ARG
 
 }  // namespace hcx

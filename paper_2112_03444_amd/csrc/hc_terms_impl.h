@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256, TermCfg<TK>::template waves<R>()) void k_track
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ __align__(16) unsigned char buf[4 * track_wave_bytes<TK, R>()];
     GridSource src{a.head, a.n_items, a.items_per_inst, a.tracks_per_item, a.n_start, false};
-    run_items<TermCfg<TK>::NM, TermCfg<TK>::G, R, PARAM, GridSource, TK>(
+    run_items<TermCfg<TK>::NM, TermCfg<TK>::G, R, PARAM, GridSource, TK, -1, true>(
         a, src, reinterpret_cast<cx<R> *>(buf + (size_t)wib * track_wave_bytes<TK, R>()));
 }
 
