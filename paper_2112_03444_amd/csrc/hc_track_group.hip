@@ -17,7 +17,11 @@ __global__ __launch_bounds__(256, PARAM ? 1 : 2) void k_track_grp(const TrackArg
     constexpr int kSlot = N * dense_terms(N);
     __shared__ __align__(16) unsigned char tab[tab_bytes<R, kSlot>()];
     GridSource src{a.head, a.n_items, a.items_per_inst, a.tracks_per_item, a.n_start, false};
-    run_items<N, G, R, PARAM>(a, src, reinterpret_cast<cx<R> *>(tab) + wib * kSlots * kSlot);
+    // n >= 5: launch constants read from the kernel-argument segment where they
+    // are used (held in scalar registers they spill to vector lanes); the short
+    // stages of n <= 4 are better off keeping them in registers
+    run_items<N, G, R, PARAM, GridSource, -1, -1, (N >= 5)>(a, src,
+                                                            reinterpret_cast<cx<R> *>(tab) + wib * kSlots * kSlot);
 }
 
 // Persistent tracker over a device work queue: each wavefront pops work items
