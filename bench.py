@@ -30,7 +30,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X published vector peaks
 # HBM bytes per tracking launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch, scaled by the
 # reading of a 512 MiB device copy in the same run), for the kernel versions profiled in profiles/; they are
 # not measured live, and a kernel changed since its counters were taken has no entry.
-PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 180.6e6, "k_track_grp<8,8,double,false>": 408.2e6}
+PROFILED_TRAFFIC_BYTES = {"k_track_grp<8,8,float,false>": 171.2e6, "k_track_grp<8,8,double,false>": 453.1e6}
 
 
 def w_lu(n: int) -> int:
